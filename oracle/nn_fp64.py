@@ -1,0 +1,231 @@
+"""FP64 / complex128 NumPy oracle of the Nested Neumann (NN) iteration.
+
+TEST INFRASTRUCTURE ONLY: used by ``tests/``, ``__graft_entry__.smoke()`` and
+``bench.py``'s CPU baseline; never by the product path.
+
+Paper: Engsig, Yang, Mehouachi, arXiv 2212.02406.
+
+What is computed (Sec. II-D, Theorem; Algorithm 1 of Sec. III):
+    starting from an initial iterate X_0 with ||I - A X_0||_2 < 1, each nest
+    (step) replaces X by X * sum_{n=0..d} (I - A X)^n, where d is the
+    inception depth L.  d = 1 is Newton's iteration (Sec. II-B), d = 2 is the
+    Chebyshev iteration (Sec. II-C; Corollary 4).
+
+Readings taken where the paper is silent or garbled (each is listed in the
+design notes of the repository):
+
+* Right form.  The paper writes the polynomial on the left,
+  sum_n (I - phi W~)^n phi.  We iterate X = Theta * phi directly with the
+  residual on the right, X * sum_n (I - A X)^n.  The two are equal in exact
+  arithmetic because X (A X)^n = (X A)^n X; ``tests/test_oracle_exact.py``
+  checks that equality in rational arithmetic.
+* Algorithm 1's "Trace(W)" is the scale 1/Tr(W) of the trace normalisation
+  (Sec. II-A), and its "1 - Z W" is I - Z W.
+* Initial iterates.  ``X0_SCALED_IDENTITY`` is the paper's own choice
+  phi^(0) = I with Theta = 1/Tr(W) (Sec. II-A, Sec. II-D), i.e.
+  X_0 = I / Re Tr(A), for Hermitian positive definite A.
+  ``X0_TRANSPOSE`` is X_0 = A^H / (||A||_1 ||A||_inf), the Pan-Schreiber
+  start that Sec. II-C and Corollary 5 refer to; it is the normal-equation
+  route of Corollary 3 (A X_0 is Hermitian PSD) and works for any
+  nonsingular A.  ``X0_GIVEN`` takes a caller-supplied X_0 (restart).
+* Accuracy measure.  rms = ||I - A X||_F / sqrt(N) ("root mean Frobenius
+  norm error", Sec. II).  The paper iterates a fixed number of nests; a
+  tolerance stop on this rms, tested before each update, is our addition.
+* Status rules (the paper has none): see ``nn_ref``.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Status codes (same values as the C ABI; defined here independently).
+OK = 0
+NOT_CONVERGED = 1
+STAGNATED = 2
+ERR_ARG = -1
+ERR_DIVERGED = -2
+ERR_NONFINITE = -3
+
+# Initial-iterate choices.
+X0_TRANSPOSE = 0
+X0_SCALED_IDENTITY = 1
+X0_GIVEN = 2
+
+
+def norm_1(A: np.ndarray) -> float:
+    """Maximum over columns of the sum of moduli (induced 1-norm)."""
+    return float(np.max(np.sum(np.abs(A), axis=0)))
+
+
+def norm_inf(A: np.ndarray) -> float:
+    """Maximum over rows of the sum of moduli (induced inf-norm)."""
+    return float(np.max(np.sum(np.abs(A), axis=1)))
+
+
+def initial_guess(A: np.ndarray, x0: int, X_init: np.ndarray | None = None):
+    """Return (den, X_0), where X_0 = X_init for GIVEN, else (1/den) * M.
+
+    * TRANSPOSE: den = ||A||_1 ||A||_inf, M = A^H.  Since
+      ||A||_2^2 <= ||A||_1 ||A||_inf, A X_0 = A A^H / den has its eigenvalues
+      in (0, 1] for nonsingular A, so ||I - A X_0||_2 < 1 (the normalisation
+      condition of Sec. II-A).
+    * SCALED_IDENTITY: den = Re Tr(A), M = I (Sec. II-A, trace
+      normalisation Theta_1, with phi^(0) = I of Sec. II-D).
+    * GIVEN: den = nan, X_0 = X_init.
+    """
+    n = A.shape[0]
+    if x0 == X0_TRANSPOSE:
+        den = norm_1(A) * norm_inf(A)
+        s = 1.0 / den if den > 0.0 and math.isfinite(den) else math.nan
+        return den, s * A.conj().T
+    if x0 == X0_SCALED_IDENTITY:
+        den = float(np.real(np.trace(A)))
+        s = 1.0 / den if den > 0.0 and math.isfinite(den) else math.nan
+        return den, s * np.eye(n, dtype=A.dtype)
+    if x0 == X0_GIVEN:
+        if X_init is None or np.shape(X_init) != A.shape:
+            raise ValueError("X0_GIVEN needs X_init of the same shape as A")
+        return math.nan, np.array(X_init, dtype=A.dtype, copy=True)
+    raise ValueError(f"unknown x0 choice {x0}")
+
+
+def residual(A: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """R = I - A X (Algorithm 1's P, in the right form)."""
+    n = A.shape[0]
+    return np.eye(n, dtype=A.dtype) - A @ X
+
+
+def rms_of(R: np.ndarray) -> float:
+    """||R||_F / sqrt(N), with |.| the complex modulus."""
+    n = R.shape[0]
+    return float(math.sqrt(float(np.sum(np.abs(R) ** 2)) / n))
+
+
+def nn_step(X: np.ndarray, R: np.ndarray, d: int) -> np.ndarray:
+    """One nest, given the residual R = I - A X of the current iterate.
+
+    Algorithm 1: S = I + sum_{l=1..L} P^l with the powers built one product
+    at a time, then the iterate is multiplied by S (right form: X S).
+    That is d - 1 products for the powers R^2..R^d plus one for X S, which
+    with the residual product gives the L + 1 products per nest of the cost
+    model of Sec. II-D.
+    """
+    n = R.shape[0]
+    S = np.eye(n, dtype=R.dtype)
+    P_l = None
+    for l in range(1, d + 1):
+        P_l = R.copy() if l == 1 else P_l @ R
+        S = S + P_l
+    return X @ S
+
+
+def nn_ref(A, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
+           max_iter: int = 100, fixed_iter: int | None = None,
+           X_init=None, trace_max: int = 1 << 20):
+    """Run the NN iteration on A; return (X, info).
+
+    info = {"iters", "rms", "status", "trace", "den"}.  ``iters`` is the
+    number of nests applied to X_0 to obtain the returned X, and ``rms`` is
+    that X's rms; ``trace`` lists rms_0, rms_1, ... as computed.
+
+    Control, for k = 0, 1, 2, ... with R_k = I - A X_k and rms_k its rms:
+
+    * fixed_iter mode (fixed_iter is not None): exactly fixed_iter nests; the
+      returned X is X_fixed_iter, status OK unless its rms is not finite.
+    * tolerance mode, tested in this order:
+        - rms_k not finite                         -> ERR_NONFINITE
+        - rms_k < tol                              -> OK (X_k returned)
+        - k > 0, rms_k >= 1 and rms_k > rms_{k-1}  -> ERR_DIVERGED
+          (a valid start keeps rms <= ||R||_2 < 1 for ever: Appendix 2)
+        - k > 0, sqrt(N) rms_{k-1} < 0.1 and rms_k >= rms_{k-1}
+                                                   -> STAGNATED, X_{k-1}
+          (then ||R_{k-1}||_2 < 0.1 and an exact nest would have taken it
+          below 0.1^(d+1); no decrease means the rounding floor)
+        - k == max_iter                            -> NOT_CONVERGED, X_k
+    * Before the loop (not for X0_GIVEN): the scale denominator den of
+      ``initial_guess`` not finite -> ERR_NONFINITE; den <= 0 -> ERR_DIVERGED
+      (the normalisation of Sec. II-A cannot hold: A = 0, or a trace that
+      is not positive, so A is not positive definite).
+    """
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 1:
+        raise ValueError("A must be a non-empty square matrix")
+    if d < 1:
+        raise ValueError("inception depth d must be >= 1")
+    if A.dtype not in (np.float64, np.complex128):
+        A = A.astype(np.complex128 if np.iscomplexobj(A) else np.float64)
+    n = A.shape[0]
+    den, X = initial_guess(A, x0, X_init)
+    info = {"iters": 0, "rms": math.nan, "status": OK, "trace": [], "den": den}
+    if x0 != X0_GIVEN:
+        if not math.isfinite(den):
+            info["status"] = ERR_NONFINITE
+            return X, info
+        if den <= 0.0:
+            info["status"] = ERR_DIVERGED
+            return X, info
+
+    X_prev, rms_prev = None, math.nan
+    k = 0
+    while True:
+        R = residual(A, X)
+        rms = rms_of(R)
+        if len(info["trace"]) < trace_max:
+            info["trace"].append(rms)
+        if fixed_iter is not None:
+            if k == fixed_iter:
+                info.update(iters=k, rms=rms,
+                            status=OK if math.isfinite(rms) else ERR_NONFINITE)
+                return X, info
+        else:
+            if not math.isfinite(rms):
+                info.update(iters=k, rms=rms, status=ERR_NONFINITE)
+                return X, info
+            if rms < tol:
+                info.update(iters=k, rms=rms, status=OK)
+                return X, info
+            if k > 0 and rms >= 1.0 and rms > rms_prev:
+                info.update(iters=k, rms=rms, status=ERR_DIVERGED)
+                return X, info
+            if k > 0 and math.sqrt(n) * rms_prev < 0.1 and rms >= rms_prev:
+                info.update(iters=k - 1, rms=rms_prev, status=STAGNATED)
+                return X_prev, info
+            if k == max_iter:
+                info.update(iters=k, rms=rms, status=NOT_CONVERGED)
+                return X, info
+        X_prev, rms_prev = X, rms
+        X = nn_step(X, R, d)
+        k += 1
+
+
+def nn_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
+                 max_iter: int = 100, fixed_iter: int | None = None):
+    """Solve A x = B (Corollary 3): x = X B with X the NN inverse of A.
+
+    With X0_TRANSPOSE this is the normal-equation route of Corollary 3
+    (A X_0 is Hermitian PSD for any nonsingular A).  Returns (x, info);
+    info also gets "rel_residual" = ||B - A x||_F / ||B||_F.
+    """
+    X, info = nn_ref(A, d=d, x0=x0, tol=tol, max_iter=max_iter, fixed_iter=fixed_iter)
+    x = X @ np.asarray(B, dtype=X.dtype)
+    bnorm = float(np.linalg.norm(B))
+    info["rel_residual"] = float(np.linalg.norm(B - A @ x)) / bnorm if bnorm > 0 else 0.0
+    return x, info
+
+
+def nn_batched_ref(mats, d: int = 2, x0: int = X0_TRANSPOSE, fixed_iter: int = 4):
+    """The batched form: each matrix of ``mats`` independently, fixed nests.
+
+    Returns (list of X, list of info).  Matrices are promoted to complex128
+    (or float64) before the iteration.
+    """
+    Xs, infos = [], []
+    for M in mats:
+        M = np.asarray(M)
+        M = M.astype(np.complex128 if np.iscomplexobj(M) else np.float64)
+        X, info = nn_ref(M, d=d, x0=x0, fixed_iter=fixed_iter)
+        Xs.append(X)
+        infos.append(info)
+    return Xs, infos

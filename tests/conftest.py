@@ -1,0 +1,16 @@
+"""Shared pytest configuration.
+
+Marker ``gpu``: the test needs an MI355X (gfx950) and the built HIP library.
+Everything else runs on the CPU (the oracle, its pins, host-side logic and the
+C-ABI symbol checks).
+"""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
