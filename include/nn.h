@@ -1,0 +1,190 @@
+/*
+ * nn.h — C ABI of the Nested Neumann (NN) matrix-inversion library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method (Engsig, Yang, Mehouachi, arXiv 2212.02406, Sec. II-D Theorem and
+ * Algorithm 1): from a start X_0 with ||I - A X_0||_2 < 1, each nest replaces
+ * X by X * sum_{n=0..d} (I - A X)^n, d being the inception depth (L in the
+ * paper).  d = 1 is Newton's iteration (Sec. II-B), d = 2 the Chebyshev
+ * iteration (Sec. II-C).  On the device a nest is d + 1 dense GEMMs:
+ *     R   = I - A X                     (residual, rms partials fused)
+ *     U_1 = R,  U_{m+1} = R + R U_m     (d - 1 GEMMs, Horner form)
+ *     X'  = X + X U_d                   (update)
+ * which equals X (I + R + ... + R^d) (Sec. II-D cost model: L + 1 products
+ * per nest).  rms = ||I - A X||_F / sqrt(N) (Sec. II, "root mean Frobenius
+ * norm error").
+ *
+ * Conventions for every entry point:
+ *  - Matrices are dense, row-major, with a leading dimension (in elements)
+ *    >= the number of columns.  Complex values are interleaved (re, im), the
+ *    layout of std::complex and of torch complex tensors.
+ *  - Pointers named A, B, X, Xsol, ws, A_packed, X_packed, offsets, sizes,
+ *    per_matrix are DEVICE pointers; `info` and `params` are HOST pointers.
+ *  - The caller owns every buffer.  The library allocates no device memory
+ *    in any entry point below except nn_create (a few pinned host bytes for
+ *    the per-nest residual read-back).  All work for one call is enqueued on
+ *    the context's stream (set by nn_create / nn_set_stream).
+ *  - A is never written.  X must not alias A or the workspace.
+ *  - Argument errors return NN_ERR_ARG before any launch, and X is left
+ *    untouched.  Positive statuses are warnings with a valid X (the last or
+ *    best iterate); negative statuses are errors and X is unspecified.
+ */
+#ifndef NN_H
+#define NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NN_OK = 0,              /* rms < tol (tolerance mode) or fixed nests done */
+  NN_NOT_CONVERGED = 1,   /* max_iter nests applied, rms >= tol; X = last iterate */
+  NN_STAGNATED = 2,       /* rounding floor reached above tol; X = best iterate */
+  NN_ERR_ARG = -1,        /* invalid argument; nothing launched */
+  NN_ERR_DIVERGED = -2,   /* rms >= 1 and growing, or the start scale is not positive */
+  NN_ERR_NONFINITE = -3,  /* NaN/Inf in A, in the start scale or in a residual */
+  NN_ERR_HIP = -4,        /* a HIP runtime call failed */
+  NN_ERR_WORKSPACE = -5,  /* workspace missing, too small or misaligned */
+  NN_ERR_UNSUPPORTED = -6 /* a valid but unimplemented combination */
+} nn_status;
+
+typedef enum {
+  NN_F64 = 0,   /* double */
+  NN_F32 = 1,   /* float */
+  NN_C64 = 2,   /* complex float, interleaved */
+  NN_C128 = 3   /* complex double, interleaved */
+} nn_dtype;
+
+typedef enum {
+  /* X_0 = A^H / (||A||_1 ||A||_inf): A X_0 is Hermitian PSD with spectrum in
+     (0, 1] for any nonsingular A (Corollary 3's normal-equation route). */
+  NN_X0_TRANSPOSE = 0,
+  /* X_0 = I / Re Tr(A): the paper's phi^(0) = I with Theta = 1/Tr(W)
+     (Sec. II-A, Sec. II-D).  Hermitian positive definite A only. */
+  NN_X0_SCALED_IDENTITY = 1,
+  /* X holds the start on entry (restart from a saved iterate). */
+  NN_X0_GIVEN = 2
+} nn_x0;
+
+typedef enum {
+  NN_PREC_PLAIN = 0, /* every GEMM in the dtype of A */
+  /* NN_F64 only: bulk nests as BF16 MFMA GEMMs with FP32 accumulation, then
+     FP32, then FP64 residual and refinement nests; X and rms in FP64. */
+  NN_PREC_MIXED = 1
+} nn_prec;
+
+#define NN_MAX_DEPTH 8
+#define NN_TRACE_MAX 128
+/* nn_params.flags bit: time every GEMM launch with a pair of HIP events on
+   the context stream and report their sum in nn_info.gemm_ms. */
+#define NN_FLAG_TIME_GEMMS 1
+
+typedef struct {
+  int32_t depth;      /* inception depth d, 1 <= d <= NN_MAX_DEPTH */
+  int32_t x0;         /* nn_x0 */
+  double tol;         /* tolerance mode: stop when rms < tol (tol >= 0) */
+  int32_t max_iter;   /* tolerance mode: at most this many nests (>= 1) */
+  int32_t fixed_iter; /* > 0: exactly this many nests, no host sync, tol and
+                         max_iter ignored; 0: tolerance mode */
+  int32_t prec;       /* nn_prec */
+  int32_t flags;      /* 0 or NN_FLAG_TIME_GEMMS; other bits must be 0 */
+} nn_params;
+
+typedef struct {
+  int32_t iters;      /* nests applied to X_0 to obtain the returned X */
+  int32_t status;     /* nn_status of the call */
+  double rms;         /* rms of the returned X */
+  float device_ms;    /* device time of the call (HIP events) */
+  float gemm_ms;      /* with NN_FLAG_TIME_GEMMS: summed duration of the GEMM
+                         launches (first 1024 of the call), else 0 */
+  int32_t gemms;      /* GEMM launches made (k (d+1) + 1 for k nests) */
+  int32_t n_trace;    /* entries used in rms_trace */
+  int32_t phase_iters[3]; /* mixed: nests in the BF16, FP32, FP64 phases */
+  double rms_trace[NN_TRACE_MAX]; /* rms_0, rms_1, ... as computed */
+} nn_info;
+
+/* Per-matrix result of nn_invert_batched, written on the device. */
+typedef struct {
+  int32_t iters;
+  int32_t status;
+  double rms;
+} nn_info_dev;
+
+typedef struct nn_ctx nn_ctx;
+
+/* Create a context bound to HIP device `device` and stream `stream` (a
+   hipStream_t; NULL = the null stream).  The stream stays owned by the
+   caller.  Allocates a few pinned host bytes.  Returns NN_ERR_ARG for a bad
+   device or ctx pointer, NN_ERR_HIP on runtime failure. */
+nn_status nn_create(nn_ctx** ctx, int device, void* stream);
+
+/* Release a context (NULL is ignored).  Does not synchronise the stream. */
+void nn_destroy(nn_ctx* ctx);
+
+/* Re-bind the context to another stream of the same device. */
+nn_status nn_set_stream(nn_ctx* ctx, void* stream);
+
+/* Workspace bytes nn_invert needs for an n x n problem (0 on bad args). */
+size_t nn_workspace_size(int64_t n, nn_dtype dtype, const nn_params* params);
+
+/* Approximate A^{-1} by the NN iteration (Sec. II-D Theorem, Algorithm 1).
+ *   A      n x n, leading dimension lda, dtype `dtype`, read only.
+ *   X      n x n, leading dimension ldx, same dtype: the result; with
+ *          NN_X0_GIVEN it holds the start on entry.
+ *   ws     device workspace of at least nn_workspace_size() bytes, 256-byte
+ *          aligned; its contents are scratch.
+ *   info   optional host pointer; filled on return.
+ * Tolerance mode blocks until the status is known (one 8-byte read-back per
+ * nest).  Fixed mode (params->fixed_iter > 0) blocks once at the end.
+ * Supported: F64, F32, C64, C128 plain; F64 mixed. */
+nn_status nn_invert(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx,
+                    int64_t n, nn_dtype dtype, const nn_params* params,
+                    void* ws, size_t ws_bytes, nn_info* info);
+
+/* Workspace bytes nn_solve needs. */
+size_t nn_solve_workspace_size(int64_t n, int64_t nrhs, nn_dtype dtype,
+                               const nn_params* params);
+
+/* Solve A Xsol = B (Corollary 3): X = NN inverse of A (kept in ws), then
+ * Xsol = X B, one n x n x nrhs GEMM.  B is n x nrhs (ldb), Xsol n x nrhs
+ * (ldx).  With NN_X0_TRANSPOSE any nonsingular A works (normal-equation
+ * route).  info->rms is the inverse's rms; the relative residual
+ * ||B - A Xsol||_F / ||B||_F is returned in *rel_residual if non-NULL. */
+nn_status nn_solve(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                   void* Xsol, int64_t ldx, int64_t n, int64_t nrhs, nn_dtype dtype,
+                   const nn_params* params, void* ws, size_t ws_bytes, nn_info* info,
+                   double* rel_residual);
+
+/* Workspace bytes nn_invert_batched needs for `batch` matrices. */
+size_t nn_batched_workspace_size(int32_t batch, nn_dtype dtype);
+
+/* Invert a batch of small matrices of uneven sizes in one persistent launch
+ * (the massive-MIMO use of Corollary 4's discussion).
+ *   A_packed, X_packed  matrices back to back, row-major, leading dimension
+ *                        = own size; matrix b starts at element offsets[b].
+ *   offsets (int64), sizes (int32): device arrays of length `batch`;
+ *                        1 <= sizes[b] <= max_n.
+ *   max_n                upper bound of sizes (<= 64).
+ *   params               fixed_iter > 0 required (tolerance mode is not
+ *                        offered for batches); x0 TRANSPOSE or
+ *                        SCALED_IDENTITY.
+ *   per_matrix           device array of `batch` nn_info_dev, or NULL.
+ * Asynchronous on the context stream; nothing is read back.  Each matrix's
+ * result depends only on that matrix (never on the rest of the batch).
+ * Supported dtypes: C64, F32. */
+nn_status nn_invert_batched(nn_ctx* ctx, const void* A_packed, void* X_packed,
+                            const int64_t* offsets, const int32_t* sizes, int32_t batch,
+                            int32_t max_n, nn_dtype dtype, const nn_params* params,
+                            void* ws, size_t ws_bytes, nn_info_dev* per_matrix);
+
+/* Static description of a status code. */
+const char* nn_status_string(nn_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NN_H */

@@ -1,0 +1,472 @@
+// nn_api.cpp — C ABI and host control of the NN library (see include/nn.h).
+//
+// The host side validates arguments, carves the caller's workspace, enqueues
+// the kernels of each nest on the caller's stream, and applies the stopping
+// rules.  The rules (the paper iterates a fixed number of nests, Algorithm 1;
+// the tolerance stop and status outcomes are this library's):
+//   before the loop:  den not finite -> NONFINITE, den <= 0 -> DIVERGED
+//   for k = 0, 1, ... with rms_k = ||I - A X_k||_F / sqrt(N):
+//     fixed mode: stop at k == fixed_iter
+//     tolerance mode, in this order:
+//       rms_k not finite                          -> NONFINITE
+//       rms_k < tol                               -> OK, X_k
+//       k > 0, rms_k >= 1, rms_k > rms_{k-1}      -> DIVERGED
+//       k > 0, sqrt(N) rms_{k-1} < 0.1, rms_k >= rms_{k-1}
+//                                                 -> STAGNATED, X_{k-1}
+//       k == max_iter                             -> NOT_CONVERGED, X_k
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "nn_internal.h"
+
+constexpr int kTimedGemms = 1024;
+
+struct nn_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double* host = nullptr;  // pinned read-back slots
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  hipEvent_t* ev_gemm = nullptr;  // 2 * kTimedGemms events, created on first timed call
+};
+
+namespace nn {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kHostSlots = NN_TRACE_MAX + 16;
+constexpr int kStatSlots = NN_TRACE_MAX + 1;
+
+inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off += up(bytes);
+    return p;
+  }
+};
+
+// Workspace regions of one plain inversion.
+struct PlainWs {
+  void* xalt = nullptr;
+  void* r = nullptr;
+  void* u0 = nullptr;
+  void* u1 = nullptr;
+  double* part = nullptr;     // per-tile partials of the residual GEMM
+  double* denpart = nullptr;  // row sums / column partial sums for the norms
+  double* scal = nullptr;     // [0] den
+  double* stats = nullptr;    // rms per nest
+  size_t bytes = 0;
+};
+
+PlainWs carve_plain(void* base, int64_t n, nn_dtype dt, int depth) {
+  Carver c(base);
+  PlainWs w;
+  const size_t mat = (size_t)n * (size_t)n * elem_size(dt);
+  const bool cplx = is_complex(dt);
+  const GemmPlan plan = plan_gemm(is_double(dt) ? Elem::F64 : Elem::F32, n, cplx ? 2 * n : n);
+  w.xalt = c.take(mat);
+  w.r = c.take(mat);
+  if (depth >= 2) w.u0 = c.take(mat);
+  if (depth >= 3) w.u1 = c.take(mat);
+  w.part = static_cast<double*>(c.take(sizeof(double) * (size_t)std::max(plan.num_tiles(), 1)));
+  w.denpart = static_cast<double*>(c.take(sizeof(double) * den_partials_elems(n)));
+  w.scal = static_cast<double*>(c.take(sizeof(double) * 8));
+  w.stats = static_cast<double*>(c.take(sizeof(double) * kStatSlots));
+  w.bytes = c.off;
+  return w;
+}
+
+bool valid_dtype(int d) { return d >= NN_F64 && d <= NN_C128; }
+
+nn_status check_params(const nn_params* p) {
+  if (!p) return NN_ERR_ARG;
+  if (p->depth < 1 || p->depth > NN_MAX_DEPTH) return NN_ERR_ARG;
+  if (p->x0 < NN_X0_TRANSPOSE || p->x0 > NN_X0_GIVEN) return NN_ERR_ARG;
+  if (p->fixed_iter < 0) return NN_ERR_ARG;
+  if (p->fixed_iter == 0) {
+    if (!(p->tol >= 0.0) || p->max_iter < 1) return NN_ERR_ARG;
+  }
+  if (p->prec != NN_PREC_PLAIN && p->prec != NN_PREC_MIXED) return NN_ERR_ARG;
+  if (p->flags & ~NN_FLAG_TIME_GEMMS) return NN_ERR_ARG;
+  return NN_OK;
+}
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return NN_ERR_HIP; \
+  } while (0)
+
+struct Ctl {
+  nn_ctx* ctx;
+  nn_dtype dt;
+  int64_t n;
+  const nn_params* prm;
+  nn_info* info;
+  int gemms = 0;
+  int timed = 0;  // GEMM launches bracketed by event pairs
+
+  bool timing() const { return (prm->flags & NN_FLAG_TIME_GEMMS) && ctx->ev_gemm; }
+  // Launch one GEMM, bracketed by events when timing is on.
+  hipError_t gemm(Elem e, bool cplx, const GemmPlan& plan, const GemmArgs& a) {
+    const bool t = timing() && timed < kTimedGemms;
+    if (t) {
+      hipError_t r = hipEventRecord(ctx->ev_gemm[2 * timed], ctx->stream);
+      if (r != hipSuccess) return r;
+    }
+    hipError_t err = launch_gemm(e, cplx, plan, a, ctx->stream);
+    if (err != hipSuccess) return err;
+    if (t) {
+      err = hipEventRecord(ctx->ev_gemm[2 * timed + 1], ctx->stream);
+      ++timed;
+    }
+    ++gemms;
+    return err;
+  }
+  float gemm_ms() const {
+    float tot = 0.f;
+    for (int i = 0; i < timed; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ctx->ev_gemm[2 * i], ctx->ev_gemm[2 * i + 1]) == hipSuccess)
+        tot += ms;
+    }
+    return tot;
+  }
+};
+
+hipError_t ensure_gemm_events(nn_ctx* ctx) {
+  if (ctx->ev_gemm) return hipSuccess;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[2 * kTimedGemms];
+  if (!ev) return hipErrorOutOfMemory;
+  for (int i = 0; i < 2 * kTimedGemms; ++i) {
+    hipError_t e = hipEventCreate(&ev[i]);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      delete[] ev;
+      return e;
+    }
+  }
+  ctx->ev_gemm = ev;
+  return hipSuccess;
+}
+
+// Residual GEMM R = I - A X with partials, then rms into stats[slot].
+hipError_t residual_rms(Ctl& c, Elem e, bool cplx, const GemmPlan& plan, const void* A,
+                        int64_t lda_r, const void* Xc, int64_t ldx_r, void* R, int64_t n,
+                        double* part, double* rms_out) {
+  const int64_t nr = cplx ? 2 * n : n;
+  GemmArgs g{A, lda_r, Xc, ldx_r, R, nr, nullptr, 0, n, nr, nr, -1.0, 1.0, part};
+  hipError_t err = c.gemm(e, cplx, plan, g);
+  if (err != hipSuccess) return err;
+  return launch_rms_reduce(part, plan.num_tiles(), n, rms_out, c.ctx->stream);
+}
+
+nn_status finish_info(Ctl& c, nn_status st, int iters, double rms, int n_trace,
+                      const double* trace) {
+  if (c.info) {
+    c.info->status = st;
+    c.info->iters = iters;
+    c.info->rms = rms;
+    c.info->gemms = c.gemms;
+    c.info->n_trace = n_trace;
+    for (int i = 0; i < n_trace && i < NN_TRACE_MAX; ++i) c.info->rms_trace[i] = trace[i];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c.ctx->ev_start, c.ctx->ev_stop) == hipSuccess)
+      c.info->device_ms = ms;
+    c.info->gemm_ms = c.gemm_ms();
+  }
+  return st;
+}
+
+// The plain NN loop: every GEMM in the dtype of A.
+nn_status run_plain(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx, int64_t n,
+                    nn_dtype dt, const nn_params* prm, const PlainWs& w, nn_info* info) {
+  hipStream_t s = ctx->stream;
+  const bool cplx = is_complex(dt);
+  const Elem e = is_double(dt) ? Elem::F64 : Elem::F32;
+  const int cm = cplx ? 2 : 1;  // real components per element
+  const int64_t nr = cm * n;
+  const GemmPlan plan = plan_gemm(e, n, nr);
+  const size_t esz = elem_size(dt);
+  Ctl c{ctx, dt, n, prm, info};
+  if (prm->flags & NN_FLAG_TIME_GEMMS) HIP_TRY(ensure_gemm_events(ctx));
+  double trace[NN_TRACE_MAX];
+  int n_trace = 0;
+
+  HIP_TRY(hipEventRecord(ctx->ev_start, s));
+  // Start iterate X_0 in the caller's X.
+  if (prm->x0 != NN_X0_GIVEN) {
+    if (prm->x0 == NN_X0_TRANSPOSE) {
+      HIP_TRY(launch_den_transpose(dt, A, lda, n, w.denpart, w.scal, s));
+      HIP_TRY(launch_x0_transpose(dt, A, lda, X, ldx, n, w.scal, s));
+    } else {
+      HIP_TRY(launch_den_trace(dt, A, lda, n, w.scal, s));
+      HIP_TRY(launch_x0_identity(dt, X, ldx, n, w.scal, s));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double den = ctx->host[0];
+    if (!isfinite(den) || den <= 0.0) {
+      HIP_TRY(hipEventRecord(ctx->ev_stop, s));
+      HIP_TRY(hipEventSynchronize(ctx->ev_stop));
+      return finish_info(c, isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE, 0, NAN, 0, trace);
+    }
+  }
+
+  void* cur = X;
+  int64_t ld_cur = ldx;
+  void* alt = w.xalt;
+  int64_t ld_alt = n;
+  const bool fixed = prm->fixed_iter > 0;
+  const int d = prm->depth;
+  double rms_prev = NAN;
+  nn_status st = NN_OK;
+  int iters = 0;
+  double rms_ret = NAN;
+  bool use_alt = false;  // result lives in `alt` (the previous iterate)
+
+  for (int k = 0;; ++k) {
+    const int slot = std::min(k, kStatSlots - 1);
+    HIP_TRY(residual_rms(c, e, cplx, plan, A, lda * cm, cur, ld_cur * cm, w.r, n, w.part,
+                         w.stats + slot));
+    if (fixed) {
+      if (k == prm->fixed_iter) {
+        iters = k;
+        break;
+      }
+    } else {
+      HIP_TRY(hipMemcpyAsync(ctx->host + 1, w.stats + slot, sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double rms = ctx->host[1];
+      if (n_trace < NN_TRACE_MAX) trace[n_trace++] = rms;
+      iters = k;
+      rms_ret = rms;
+      if (!isfinite(rms)) { st = NN_ERR_NONFINITE; break; }
+      if (rms < prm->tol) { st = NN_OK; break; }
+      if (k > 0 && rms >= 1.0 && rms > rms_prev) { st = NN_ERR_DIVERGED; break; }
+      if (k > 0 && sqrt((double)n) * rms_prev < 0.1 && rms >= rms_prev) {
+        st = NN_STAGNATED;
+        iters = k - 1;
+        rms_ret = rms_prev;
+        use_alt = true;
+        break;
+      }
+      if (k == prm->max_iter) { st = NN_NOT_CONVERGED; break; }
+      rms_prev = rms;
+    }
+    // Horner chain U_1 = R, U_{m+1} = R + R U_m, ping-pong between u0/u1.
+    const void* U = w.r;
+    for (int m = 1; m < d; ++m) {
+      void* Un = (m & 1) ? w.u0 : w.u1;
+      GemmArgs g{w.r, nr, U, nr, Un, nr, w.r, nr, n, nr, nr, 1.0, 0.0, nullptr};
+      HIP_TRY(c.gemm(e, cplx, plan, g));
+      U = Un;
+    }
+    // Update X' = X + X U_d into the other buffer.
+    GemmArgs g{cur, ld_cur * cm, U, nr, alt, ld_alt * cm, cur, ld_cur * cm, n, nr, nr, 1.0, 0.0,
+               nullptr};
+    HIP_TRY(c.gemm(e, cplx, plan, g));
+    std::swap(cur, alt);
+    std::swap(ld_cur, ld_alt);
+  }
+
+  void* res = use_alt ? alt : cur;
+  const int64_t ld_res = use_alt ? ld_alt : ld_cur;
+  if (res != X)
+    HIP_TRY(hipMemcpy2DAsync(X, (size_t)ldx * esz, res, (size_t)ld_res * esz, (size_t)n * esz,
+                             (size_t)n, hipMemcpyDeviceToDevice, s));
+  if (fixed) {
+    const int cnt = std::min(prm->fixed_iter + 1, kStatSlots);
+    HIP_TRY(hipMemcpyAsync(ctx->host + 2, w.stats, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipEventRecord(ctx->ev_stop, s));
+  HIP_TRY(hipEventSynchronize(ctx->ev_stop));
+  if (fixed) {
+    const int cnt = std::min(prm->fixed_iter + 1, kStatSlots);
+    n_trace = std::min(cnt, NN_TRACE_MAX);
+    for (int i = 0; i < n_trace; ++i) trace[i] = ctx->host[2 + i];
+    rms_ret = ctx->host[2 + cnt - 1];
+    st = isfinite(rms_ret) ? NN_OK : NN_ERR_NONFINITE;
+  }
+  return finish_info(c, st, iters, rms_ret, n_trace, trace);
+}
+
+nn_status validate_invert(nn_ctx* ctx, const void* A, int64_t lda, const void* X, int64_t ldx,
+                          int64_t n, nn_dtype dt, const nn_params* prm) {
+  if (!ctx || !A || !X || n < 1 || lda < n || ldx < n) return NN_ERR_ARG;
+  if (!valid_dtype(dt)) return NN_ERR_ARG;
+  if (check_params(prm) != NN_OK) return NN_ERR_ARG;
+  if (A == X) return NN_ERR_ARG;
+  if (dt == NN_C128 && ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(X)) & 15u))
+    return NN_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(X)) % (elem_size(dt) / (is_complex(dt) ? 2 : 1)))
+    return NN_ERR_ARG;
+  return NN_OK;
+}
+
+}  // namespace
+
+// Implemented in nn_mixed.cpp.
+size_t mixed_workspace_size(int64_t n, const nn_params* prm);
+nn_status run_mixed(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx, int64_t n,
+                    const nn_params* prm, void* ws, size_t ws_bytes, nn_info* info);
+
+}  // namespace nn
+
+using namespace nn;
+
+extern "C" {
+
+nn_status nn_create(nn_ctx** out, int device, void* stream) {
+  if (!out) return NN_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return NN_ERR_HIP;
+  if (device < 0 || device >= count) return NN_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return NN_ERR_HIP;
+  nn_ctx* c = new (std::nothrow) nn_ctx();
+  if (!c) return NN_ERR_HIP;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * kHostSlots,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess) {
+    nn_destroy(c);
+    return NN_ERR_HIP;
+  }
+  *out = c;
+  return NN_OK;
+}
+
+void nn_destroy(nn_ctx* c) {
+  if (!c) return;
+  if (c->host) (void)hipHostFree(c->host);
+  if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+  if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
+  if (c->ev_gemm) {
+    for (int i = 0; i < 2 * kTimedGemms; ++i) (void)hipEventDestroy(c->ev_gemm[i]);
+    delete[] c->ev_gemm;
+  }
+  delete c;
+}
+
+nn_status nn_set_stream(nn_ctx* c, void* stream) {
+  if (!c) return NN_ERR_ARG;
+  c->stream = static_cast<hipStream_t>(stream);
+  return NN_OK;
+}
+
+size_t nn_workspace_size(int64_t n, nn_dtype dt, const nn_params* prm) {
+  if (n < 1 || !valid_dtype(dt) || check_params(prm) != NN_OK) return 0;
+  if (prm->prec == NN_PREC_MIXED) return dt == NN_F64 ? mixed_workspace_size(n, prm) : 0;
+  return carve_plain(nullptr, n, dt, prm->depth).bytes;
+}
+
+nn_status nn_invert(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx, int64_t n,
+                    nn_dtype dt, const nn_params* prm, void* ws, size_t ws_bytes, nn_info* info) {
+  nn_status v = validate_invert(ctx, A, lda, X, ldx, n, dt, prm);
+  if (v != NN_OK) return v;
+  if (info) memset(info, 0, sizeof(*info));
+  if (prm->prec == NN_PREC_MIXED) {
+    if (dt != NN_F64) return NN_ERR_UNSUPPORTED;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) ||
+        ws_bytes < mixed_workspace_size(n, prm))
+      return NN_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NN_ERR_HIP;
+    return run_mixed(ctx, A, lda, X, ldx, n, prm, ws, ws_bytes, info);
+  }
+  const size_t need = carve_plain(nullptr, n, dt, prm->depth).bytes;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) || ws_bytes < need)
+    return NN_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return NN_ERR_HIP;
+  const PlainWs w = carve_plain(ws, n, dt, prm->depth);
+  return run_plain(ctx, A, lda, X, ldx, n, dt, prm, w, info);
+}
+
+size_t nn_solve_workspace_size(int64_t n, int64_t nrhs, nn_dtype dt, const nn_params* prm) {
+  if (n < 1 || nrhs < 1 || !valid_dtype(dt) || check_params(prm) != NN_OK) return 0;
+  if (prm->prec != NN_PREC_PLAIN || prm->x0 == NN_X0_GIVEN) return 0;
+  const size_t esz = elem_size(dt);
+  const size_t inv = up((size_t)n * n * esz);
+  const size_t rb = up((size_t)n * nrhs * esz);
+  const int cm = is_complex(dt) ? 2 : 1;
+  const GemmPlan plan =
+      plan_gemm(is_double(dt) ? Elem::F64 : Elem::F32, n, (int64_t)cm * nrhs);
+  const size_t part = up(sizeof(double) * std::max(plan.num_tiles(), 256)) + up(sizeof(double) * 8);
+  return inv + rb + part + carve_plain(nullptr, n, dt, prm->depth).bytes;
+}
+
+nn_status nn_solve(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                   void* Xsol, int64_t ldx, int64_t n, int64_t nrhs, nn_dtype dt,
+                   const nn_params* prm, void* ws, size_t ws_bytes, nn_info* info,
+                   double* rel_residual) {
+  if (!ctx || !A || !B || !Xsol || n < 1 || nrhs < 1 || lda < n || ldb < nrhs || ldx < nrhs)
+    return NN_ERR_ARG;
+  if (!valid_dtype(dt) || check_params(prm) != NN_OK) return NN_ERR_ARG;
+  if (prm->prec != NN_PREC_PLAIN || prm->x0 == NN_X0_GIVEN) return NN_ERR_UNSUPPORTED;
+  if (Xsol == B || Xsol == A) return NN_ERR_ARG;
+  const size_t need = nn_solve_workspace_size(n, nrhs, dt, prm);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) || ws_bytes < need)
+    return NN_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return NN_ERR_HIP;
+  const size_t esz = elem_size(dt);
+  Carver c(ws);
+  void* Xinv = c.take((size_t)n * n * esz);
+  void* Rb = c.take((size_t)n * nrhs * esz);
+  const int cm = is_complex(dt) ? 2 : 1;
+  const Elem e = is_double(dt) ? Elem::F64 : Elem::F32;
+  const GemmPlan plan = plan_gemm(e, n, (int64_t)cm * nrhs);
+  double* part = static_cast<double*>(c.take(sizeof(double) * std::max(plan.num_tiles(), 256)));
+  double* scal = static_cast<double*>(c.take(sizeof(double) * 8));
+  void* rest = c.base + c.off;
+  const PlainWs w = carve_plain(rest, n, dt, prm->depth);
+  nn_info local;
+  nn_info* inf = info ? info : &local;
+  nn_status st = run_plain(ctx, A, lda, Xinv, n, n, dt, prm, w, inf);
+  if (st < 0) return st;
+  hipStream_t s = ctx->stream;
+  const bool cplx = is_complex(dt);
+  // Xsol = Xinv B  (n x n times n x nrhs).
+  GemmArgs g{Xinv, (int64_t)cm * n, B, (int64_t)cm * ldb, Xsol, (int64_t)cm * ldx, nullptr, 0, n,
+             (int64_t)cm * nrhs, (int64_t)cm * n, 1.0, 0.0, nullptr};
+  HIP_TRY(launch_gemm(e, cplx, plan, g, s));
+  if (rel_residual) {
+    // Rb = B - A Xsol with partials -> ||Rb||_F; ||B||_F by a plain sum of squares.
+    GemmArgs r{A, (int64_t)cm * lda, Xsol, (int64_t)cm * ldx, Rb, (int64_t)cm * nrhs, B,
+               (int64_t)cm * ldb, n, (int64_t)cm * nrhs, (int64_t)cm * n, -1.0, 0.0, part};
+    HIP_TRY(launch_gemm(e, cplx, plan, r, s));
+    HIP_TRY(launch_rms_reduce(part, plan.num_tiles(), 1, scal, s));
+    HIP_TRY(launch_sumsq(B, is_double(dt), (int64_t)cm * ldb, n, (int64_t)cm * nrhs, part,
+                         scal + 1, s));
+    HIP_TRY(hipMemcpyAsync(ctx->host, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rel_residual) *rel_residual = ctx->host[1] > 0 ? ctx->host[0] / ctx->host[1] : 0.0;
+  return st;
+}
+
+const char* nn_status_string(nn_status s) {
+  switch (s) {
+    case NN_OK: return "ok";
+    case NN_NOT_CONVERGED: return "not converged: max_iter reached above tol";
+    case NN_STAGNATED: return "stagnated: rounding floor reached above tol";
+    case NN_ERR_ARG: return "invalid argument";
+    case NN_ERR_DIVERGED: return "diverged: start iterate violates ||I - A X0||_2 < 1";
+    case NN_ERR_NONFINITE: return "non-finite value in A, the start scale or a residual";
+    case NN_ERR_HIP: return "HIP runtime error";
+    case NN_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case NN_ERR_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

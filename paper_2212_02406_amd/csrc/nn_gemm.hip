@@ -1,0 +1,314 @@
+// nn_gemm.hip — MFMA GEMM with the fused epilogues of one NN nest (gfx950).
+//
+// One nest of the Nested Neumann iteration (arXiv 2212.02406, Sec. II-D
+// Theorem; Algorithm 1) is d + 1 dense products.  All of them are
+//     C = alpha * (A B) + E + diag * I
+// with (alpha, E, diag) = (-1, -, 1) for the residual R = I - A X,
+// (1, R, 0) for a Horner step U' = R + R U, and (1, X, 0) for the update
+// X' = X + X U.  The identity is never stored; it is added on the diagonal in
+// the epilogue.  The residual launch also writes one FP64 partial sum of
+// |C_ij|^2 per output tile into a fixed slot (no atomics), which a second
+// kernel reduces in a fixed order, so rms is bitwise reproducible.
+//
+// Kernel structure (CDNA4, wave64):
+//  * macro tile BM x BN per workgroup, WM x WN waves, each wave owns a
+//    (BM/WM) x (BN/WN) sub-tile made of 16x16 MFMA blocks
+//    (v_mfma_f64_16x16x4_f64 for FP64, v_mfma_f32_16x16x4_f32 for FP32);
+//  * A and B k-slabs of depth BK are staged global -> registers -> LDS with
+//    two LDS buffers, so one barrier per slab suffices and the next slab's
+//    global loads are in flight while the current one feeds the MFMAs;
+//  * LDS rows are padded by 16 bytes, which makes the 16-lane fragment reads
+//    bank-conflict free and keeps 16-byte vector stores aligned;
+//  * workgroup -> tile mapping is XCD-aware (each of the 8 XCDs gets a
+//    contiguous range of tiles, so the tiles sharing A and B panels share an
+//    L2) and grouped by GROUP_M tile rows inside that range.
+//  * complex matrices: C = A B in complex arithmetic equals the real product
+//    of the interleaved A (M x 2K) with the real 2K x 2N form of B whose row
+//    2k is B's row k as stored and row 2k+1 is the same row with each pair
+//    (re, im) replaced by (-im, re).  That expansion is done while staging B.
+#include "nn_internal.h"
+
+namespace nn {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+// Both 16x16x4 MFMAs take A[m][k] from lane m + 16 k and B[k][n] from lane
+// n + 16 k, and return column n = lane % 16 of D.  They differ in the rows
+// a lane's four results belong to (measured on gfx950): FP32 gives rows
+// 4 (lane / 16) + t, FP64 gives rows lane / 16 + 4 t, t = 0..3.
+template <>
+struct Mfma<double> {
+  using acc_t = d4_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int t) { return lk + 4 * t; }
+};
+template <>
+struct Mfma<float> {
+  using acc_t = f4_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int t) { return 4 * lk + t; }
+};
+
+template <typename T, int V>
+struct VecOf {
+  typedef T type __attribute__((ext_vector_type(V)));
+};
+template <typename T>
+struct VecOf<T, 1> {
+  typedef T type;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ T& lane_of(typename VecOf<T, V>::type& v, int e) {
+  return reinterpret_cast<T*>(&v)[e];
+}
+
+constexpr int kGroupM = 8;
+
+__device__ __forceinline__ int xcd_remap(int bid, int nwg) {
+  const int q = nwg / kNumXcd, r = nwg % kNumXcd;
+  const int x = bid % kNumXcd, local = bid / kNumXcd;
+  return x * q + (x < r ? x : r) + local;
+}
+
+__device__ __forceinline__ void grouped_tile(int tile, int tm, int tn, int& pm, int& pn) {
+  const int group = kGroupM * tn;
+  const int gid = tile / group;
+  const int first = gid * kGroupM;
+  const int gsize = (tm - first) < kGroupM ? (tm - first) : kGroupM;
+  const int in = tile - gid * group;
+  pm = first + in % gsize;
+  pn = in / gsize;
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, int VEC, bool CPLX>
+__global__ void __launch_bounds__(WM* WN * 64)
+    gemm_kernel(GemmArgs p, int tiles_m, int tiles_n) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int PAD = 16 / (int)sizeof(T);
+  constexpr int LAS = BK + PAD;  // As row stride ([m][k] layout)
+  constexpr int LBS = BN + PAD;  // Bs row stride ([k][n] layout)
+  constexpr int A_VPR = BK / VEC, B_VPR = BN / VEC;
+  constexpr int A_LOADS = BM * A_VPR / NT, B_LOADS = BK * B_VPR / NT;
+  static_assert(BM * A_VPR % NT == 0 && BK * B_VPR % NT == 0, "load split");
+  static_assert(BK % 4 == 0 && WTM % 16 == 0 && WTN % 16 == 0, "mfma shape");
+  static_assert(!CPLX || VEC % 2 == 0, "complex staging needs pairs");
+  using acc_t = typename Mfma<T>::acc_t;
+  using vec_t = typename VecOf<T, VEC>::type;
+
+  __shared__ __attribute__((aligned(16))) T As[2][BM * LAS];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BK * LBS];
+  __shared__ double red[WM * WN];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  int pm, pn;
+  grouped_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, pm, pn);
+  const int64_t m0 = (int64_t)pm * BM, n0 = (int64_t)pn * BN;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const T* __restrict__ A = static_cast<const T*>(p.A);
+  const T* __restrict__ B = static_cast<const T*>(p.B);
+
+  acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{};
+
+  vec_t ra[A_LOADS], rb[B_LOADS];
+
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int v = tid + i * NT;
+      const int r = v / A_VPR, c = (v % A_VPR) * VEC;
+      const int64_t gr = m0 + r, gc = k0 + c;
+      if (gr < M && gc + VEC <= K) {
+        ra[i] = *reinterpret_cast<const vec_t*>(A + gr * p.lda + gc);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          lane_of<T, VEC>(ra[i], e) = (gr < M && gc + e < K) ? A[gr * p.lda + gc + e] : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int v = tid + i * NT;
+      const int r = v / B_VPR, c = (v % B_VPR) * VEC;
+      const int64_t gr = k0 + r, gc = n0 + c;
+      const int64_t srow = CPLX ? (gr >> 1) : gr;
+      if (gr < K && gc + VEC <= N) {
+        rb[i] = *reinterpret_cast<const vec_t*>(B + srow * p.ldb + gc);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          lane_of<T, VEC>(rb[i], e) = (gr < K && gc + e < N) ? B[srow * p.ldb + gc + e] : T(0);
+      }
+      if constexpr (CPLX) {
+        if (gr & 1) {
+#pragma unroll
+          for (int e = 0; e < VEC; e += 2) {
+            const T re = lane_of<T, VEC>(rb[i], e), im = lane_of<T, VEC>(rb[i], e + 1);
+            lane_of<T, VEC>(rb[i], e) = -im;
+            lane_of<T, VEC>(rb[i], e + 1) = re;
+          }
+        }
+      }
+    }
+  };
+
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int v = tid + i * NT;
+      const int r = v / A_VPR, c = (v % A_VPR) * VEC;
+      *reinterpret_cast<vec_t*>(&As[buf][r * LAS + c]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int v = tid + i * NT;
+      const int r = v / B_VPR, c = (v % B_VPR) * VEC;
+      *reinterpret_cast<vec_t*>(&Bs[buf][r * LBS + c]) = rb[i];
+    }
+  };
+
+  const int nk = (int)((K + BK - 1) / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+    const T* as = As[cur] + (wm * WTM + lr) * LAS + lk;
+    const T* bs = Bs[cur] + lk * LBS + wn * WTN + lr;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      T af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = as[i * 16 * LAS + kk * 4];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bf[j] = bs[kk * 4 * LBS + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[i], bf[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: C = alpha * acc + E + diag * I, and the tile's sum of squares.
+  T* __restrict__ C = static_cast<T*>(p.C);
+  const T* __restrict__ E = static_cast<const T*>(p.E);
+  const T alpha = (T)p.alpha, diag = (T)p.diag;
+  double ss = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t c = n0 + wn * WTN + j * 16 + lr;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t r = m0 + wm * WTM + i * 16 + Mfma<T>::row(lk, t);
+        if (r < M && c < N) {
+          T v = alpha * acc[i][j][t];
+          if (E) v += E[r * p.lde + c];
+          if (CPLX ? (c == 2 * r) : (c == r)) v += diag;
+          C[r * p.ldc + c] = v;
+          ss += (double)v * (double)v;
+        }
+      }
+    }
+  }
+  if (p.partials) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < WM * WN; ++w) t += red[w];
+      p.partials[pm * tiles_n + pn] = t;
+    }
+  }
+}
+
+struct TileShape {
+  int bm, bn;
+};
+inline TileShape shape_of(Tile t) {
+  switch (t) {
+    case Tile::T128: return {128, 128};
+    case Tile::T64: return {64, 64};
+    case Tile::T32: return {32, 32};
+  }
+  return {32, 32};
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, int VEC, bool CPLX>
+hipError_t launch_one(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
+  const int grid = plan.num_tiles();
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, VEC, CPLX>), dim3(grid),
+                     dim3(WM * WN * 64), 0, s, a, plan.tiles_m, plan.tiles_n);
+  return hipGetLastError();
+}
+
+template <typename T, int VEC, bool CPLX>
+hipError_t launch_tile(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
+  switch (plan.tile) {
+    case Tile::T128: return launch_one<T, 128, 128, 16, 2, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T64: return launch_one<T, 64, 64, 16, 2, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T32: return launch_one<T, 32, 32, 16, 1, 1, VEC, CPLX>(plan, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+GemmPlan plan_gemm(Elem e, int64_t M, int64_t N) {
+  (void)e;
+  auto tiles = [&](int b) { return (int)(((M + b - 1) / b) * ((N + b - 1) / b)); };
+  GemmPlan p;
+  if (tiles(128) >= 256) p.tile = Tile::T128;
+  else if (tiles(64) >= 128) p.tile = Tile::T64;
+  else p.tile = Tile::T32;
+  const TileShape sh = shape_of(p.tile);
+  p.tiles_m = (int)((M + sh.bm - 1) / sh.bm);
+  p.tiles_n = (int)((N + sh.bn - 1) / sh.bn);
+  return p;
+}
+
+hipError_t launch_gemm(Elem e, bool cplx, const GemmPlan& plan, const GemmArgs& a,
+                       hipStream_t s) {
+  const bool al = aligned16(a.A) && aligned16(a.B);
+  if (e == Elem::F64) {
+    const bool v2 = al && a.lda % 2 == 0 && a.ldb % 2 == 0;
+    if (cplx) return launch_tile<double, 2, true>(plan, a, s);  // 16-byte complex elements
+    return v2 ? launch_tile<double, 2, false>(plan, a, s) : launch_tile<double, 1, false>(plan, a, s);
+  }
+  if (e == Elem::F32) {
+    const bool v4 = al && a.lda % 4 == 0 && a.ldb % 4 == 0;
+    if (cplx)
+      return v4 ? launch_tile<float, 4, true>(plan, a, s) : launch_tile<float, 2, true>(plan, a, s);
+    return v4 ? launch_tile<float, 4, false>(plan, a, s) : launch_tile<float, 1, false>(plan, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nn

@@ -1,0 +1,102 @@
+// Internal declarations of the NN library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/nn.h"
+
+namespace nn {
+
+// Number of XCDs of an MI355X; workgroups are dealt round-robin to them.
+constexpr int kNumXcd = 8;
+
+// Epilogue of a GEMM C = alpha * (A B) + E + diag * I (E optional), with an
+// optional per-tile sum of |C_ij|^2 written to partials[tile] (FP64).
+struct GemmArgs {
+  const void* A;
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  void* C;
+  int64_t ldc;
+  const void* E;  // may be null
+  int64_t lde;
+  int64_t M, N, K;  // real (not complex) extents of the product
+  double alpha;
+  double diag;
+  double* partials;  // may be null
+};
+
+enum class Elem { F64, F32, BF16IN_F32OUT };
+
+// Tile configurations selectable by the host.
+enum class Tile { T128, T64, T32 };
+
+struct GemmPlan {
+  Tile tile;
+  int tiles_m, tiles_n;
+  int num_tiles() const { return tiles_m * tiles_n; }
+};
+
+// Plan (tile choice, grid) for a real M x N product.
+GemmPlan plan_gemm(Elem e, int64_t M, int64_t N);
+
+// Enqueue C = alpha A B + E + diag I on `stream`.  `complex_b` expands B on
+// the fly into the real 2K x 2N form of a complex matrix (A, C, E are then
+// the interleaved real views of complex matrices, K and N real extents).
+hipError_t launch_gemm(Elem e, bool complex_b, const GemmPlan& plan, const GemmArgs& a,
+                       hipStream_t stream);
+
+// X_0 prologue.  scal[0] <- den (||A||_1 ||A||_inf or Re Tr A).
+hipError_t launch_den_transpose(nn_dtype dt, const void* A, int64_t lda, int64_t n, double* part,
+                                double* scal, hipStream_t s);
+hipError_t launch_den_trace(nn_dtype dt, const void* A, int64_t lda, int64_t n, double* scal,
+                            hipStream_t s);
+size_t den_partials_elems(int64_t n);
+// X = A^H / den  or  X = I / den, den read from scal[0] on the device.
+hipError_t launch_x0_transpose(nn_dtype dt, const void* A, int64_t lda, void* X, int64_t ldx,
+                               int64_t n, const double* scal, hipStream_t s);
+hipError_t launch_x0_identity(nn_dtype dt, void* X, int64_t ldx, int64_t n, const double* scal,
+                              hipStream_t s);
+
+// Sum `count` FP64 partials in a fixed order; out[0] <- sqrt(sum / n_rows).
+hipError_t launch_rms_reduce(const double* partials, int count, int64_t n_rows, double* out,
+                             hipStream_t s);
+
+// Element-wise copies/casts of an n x n (real extents rows x cols) matrix.
+hipError_t launch_copy(size_t elem_bytes, const void* src, int64_t lds, void* dst, int64_t ldd,
+                       int64_t rows, int64_t cols_bytes, hipStream_t s);
+hipError_t launch_cast_f64_f32(const double* src, int64_t lds, float* dst, int64_t ldd,
+                               int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_cast_f32_f64(const float* src, int64_t lds, double* dst, int64_t ldd,
+                               int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_cast_f64_bf16(const double* src, int64_t lds, uint16_t* dst, int64_t ldd,
+                                int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_cast_f32_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd,
+                                int64_t rows, int64_t cols, hipStream_t s);
+
+// Sum of squares of an rows x cols real matrix into out[0] (fixed order).
+hipError_t launch_sumsq(const void* src, bool f64, int64_t ld, int64_t rows, int64_t cols,
+                        double* part, double* out, hipStream_t s);
+
+// Batched persistent kernel.
+hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* offsets,
+                          const int32_t* sizes, int32_t batch, int32_t max_n, int depth,
+                          int x0, int iters, int32_t* queue, nn_info_dev* info,
+                          hipStream_t s);
+
+inline size_t elem_size(nn_dtype d) {
+  switch (d) {
+    case NN_F64: return 8;
+    case NN_F32: return 4;
+    case NN_C64: return 8;
+    case NN_C128: return 16;
+  }
+  return 0;
+}
+inline bool is_complex(nn_dtype d) { return d == NN_C64 || d == NN_C128; }
+inline bool is_double(nn_dtype d) { return d == NN_F64 || d == NN_C128; }
+
+}  // namespace nn

@@ -1,0 +1,290 @@
+"""ctypes binding of libnn.so (include/nn.h) — argument marshalling only.
+
+Every step of the NN iteration runs in the HIP library.  PyTorch is used here
+for device memory (tensors, workspace) and streams only.  If libnn.so has not
+been built this module raises ImportError: there is no fallback path.
+
+Low level: ``lib`` exposes the C entry points with the same names
+(``nn_create``, ``nn_invert``, ``nn_solve``, ``nn_invert_batched``, ...).
+High level: ``invert``, ``solve``, ``invert_batched`` take torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnn.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "nn.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_02406_amd.build`")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+# ---- enums (values from include/nn.h) --------------------------------------
+NN_OK, NN_NOT_CONVERGED, NN_STAGNATED = 0, 1, 2
+NN_ERR_ARG, NN_ERR_DIVERGED, NN_ERR_NONFINITE = -1, -2, -3
+NN_ERR_HIP, NN_ERR_WORKSPACE, NN_ERR_UNSUPPORTED = -4, -5, -6
+NN_F64, NN_F32, NN_C64, NN_C128 = 0, 1, 2, 3
+NN_X0_TRANSPOSE, NN_X0_SCALED_IDENTITY, NN_X0_GIVEN = 0, 1, 2
+NN_PREC_PLAIN, NN_PREC_MIXED = 0, 1
+NN_MAX_DEPTH = 8
+NN_TRACE_MAX = 128
+NN_FLAG_TIME_GEMMS = 1
+
+X0_NAMES = {"transpose": NN_X0_TRANSPOSE, "identity": NN_X0_SCALED_IDENTITY,
+            "scaled_identity": NN_X0_SCALED_IDENTITY, "given": NN_X0_GIVEN}
+
+
+class nn_params(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("x0", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("fixed_iter", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class nn_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rms", ctypes.c_double),
+                ("device_ms", ctypes.c_float), ("gemm_ms", ctypes.c_float),
+                ("gemms", ctypes.c_int32),
+                ("n_trace", ctypes.c_int32), ("phase_iters", ctypes.c_int32 * 3),
+                ("rms_trace", ctypes.c_double * NN_TRACE_MAX)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "status": self.status, "rms": self.rms,
+                "device_ms": self.device_ms, "gemm_ms": self.gemm_ms, "gemms": self.gemms,
+                "phase_iters": list(self.phase_iters),
+                "trace": [self.rms_trace[i] for i in range(self.n_trace)]}
+
+
+class nn_info_dev(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rms", ctypes.c_double)]
+
+
+_p, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+_PP = ctypes.POINTER(nn_params)
+_SIGS = {
+    "nn_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, _p]),
+    "nn_destroy": (None, [_p]),
+    "nn_set_stream": (ctypes.c_int, [_p, _p]),
+    "nn_workspace_size": (_sz, [_i64, ctypes.c_int, _PP]),
+    "nn_invert": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _i64, ctypes.c_int, _PP, _p, _sz,
+                                 ctypes.POINTER(nn_info)]),
+    "nn_solve_workspace_size": (_sz, [_i64, _i64, ctypes.c_int, _PP]),
+    "nn_solve": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i64, _i64, ctypes.c_int, _PP,
+                                _p, _sz, ctypes.POINTER(nn_info), ctypes.POINTER(ctypes.c_double)]),
+    "nn_batched_workspace_size": (_sz, [_i32, ctypes.c_int]),
+    "nn_invert_batched": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
+                                         _sz, _p]),
+    "nn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+def header_functions(path: str = HEADER_PATH):
+    """Names of the functions include/nn.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nn_[a-z_]+)\s*\(", text)))
+
+
+def status_string(st: int) -> str:
+    return nn_status_string(st).decode()
+
+
+class NNError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+def make_params(depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, prec="plain",
+                flags=0):
+    if isinstance(x0, str):
+        x0 = X0_NAMES[x0]
+    p = nn_params()
+    p.depth, p.x0, p.tol, p.max_iter = int(depth), int(x0), float(tol), int(max_iter)
+    p.fixed_iter = int(fixed_iter)
+    p.prec = NN_PREC_MIXED if prec in ("mixed", NN_PREC_MIXED) else NN_PREC_PLAIN
+    p.flags = int(flags)
+    return p
+
+
+# ---- torch-facing helpers (plumbing) ----------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.float64: NN_F64, torch.float32: NN_F32, torch.complex64: NN_C64,
+         torch.complex128: NN_C128}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+class Context:
+    """An nn_ctx bound to a device and a stream (default: torch's current)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        self._ptr = ctypes.c_void_p()
+        st = nn_create(ctypes.byref(self._ptr), int(device), ctypes.c_void_p(handle))
+        if st != NN_OK:
+            raise NNError(st, "nn_create")
+        self.device = device
+        self.stream = stream
+
+    @property
+    def ptr(self):
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            nn_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_CTX = {}
+
+
+def default_context(device: int = 0) -> Context:
+    torch = _torch()
+    key = (device, torch.cuda.current_stream(device).cuda_stream)
+    if key not in _CTX:
+        _CTX[key] = Context(device)
+    return _CTX[key]
+
+
+def workspace(nbytes: int, device) :
+    """A 256-byte aligned device byte buffer of at least nbytes (torch-owned)."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off, int(nbytes)
+
+
+def invert(A, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, prec="plain",
+           X=None, ctx: Context | None = None, ws=None, check=True, flags=0):
+    """X ~ A^-1 by nn_invert.  Returns (X, info dict).
+
+    A: square CUDA tensor (float64, float32, complex64, complex128), row-major
+    with any leading dimension (stride(1) must be 1).  With x0="given", X
+    holds the start iterate.
+    """
+    torch = _torch()
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("A must be a square row-major matrix")
+    n = A.shape[0]
+    dt = dtype_code(A)
+    prm = make_params(depth, x0, tol, max_iter, fixed_iter, prec, flags)
+    if X is None:
+        X = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    elif X.shape != A.shape or X.dtype != A.dtype or X.stride(1) != 1:
+        raise ValueError("X must be a row-major matrix of A's shape and dtype")
+    ctx = ctx or default_context(A.device.index or 0)
+    need = nn_workspace_size(n, dt, ctypes.byref(prm))
+    if need == 0:
+        raise NNError(NN_ERR_ARG, "nn_workspace_size")
+    hold = None
+    if ws is None:
+        hold, ws_ptr, ws_bytes = workspace(need, A.device)
+    else:
+        hold, ws_ptr, ws_bytes = ws
+    info = nn_info()
+    st = nn_invert(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.stride(0),
+                   ctypes.c_void_p(X.data_ptr()), X.stride(0), n, dt, ctypes.byref(prm),
+                   ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.byref(info))
+    del hold
+    d = info.as_dict()
+    d["status"] = st
+    if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
+        raise NNError(st, "nn_invert")
+    return X, d
+
+
+def solve(A, B, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0,
+          ctx: Context | None = None, check=True):
+    """Xsol with A Xsol = B by nn_solve (Corollary 3).  Returns (Xsol, info)."""
+    torch = _torch()
+    n, nrhs = B.shape
+    dt = dtype_code(A)
+    prm = make_params(depth, x0, tol, max_iter, fixed_iter)
+    Xs = torch.empty((n, nrhs), dtype=A.dtype, device=A.device)
+    ctx = ctx or default_context(A.device.index or 0)
+    need = nn_solve_workspace_size(n, nrhs, dt, ctypes.byref(prm))
+    if need == 0:
+        raise NNError(NN_ERR_ARG, "nn_solve_workspace_size")
+    hold, ws_ptr, ws_bytes = workspace(need, A.device)
+    info = nn_info()
+    rel = ctypes.c_double(0.0)
+    st = nn_solve(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.stride(0),
+                  ctypes.c_void_p(B.data_ptr()), B.stride(0), ctypes.c_void_p(Xs.data_ptr()),
+                  Xs.stride(0), n, nrhs, dt, ctypes.byref(prm), ctypes.c_void_p(ws_ptr),
+                  ws_bytes, ctypes.byref(info), ctypes.byref(rel))
+    del hold
+    d = info.as_dict()
+    d["status"] = st
+    d["rel_residual"] = rel.value
+    if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
+        raise NNError(st, "nn_solve")
+    return Xs, d
+
+
+def invert_batched(packed, offsets, sizes, max_n, depth=2, x0="transpose", fixed_iter=4,
+                   X=None, info=None, ctx: Context | None = None, ws=None, check=True):
+    """nn_invert_batched on packed device buffers.  Returns (X_packed, info tensor).
+
+    packed: 1-D complex64/float32 CUDA tensor; offsets int64 and sizes int32
+    CUDA tensors.  info: (batch, 2) int32 + rms as a (batch,) float64 view of
+    an nn_info_dev array (returned as a raw uint8 tensor of batch*16 bytes).
+    """
+    torch = _torch()
+    batch = int(sizes.numel())
+    dt = dtype_code(packed)
+    prm = make_params(depth, x0, 0.0, 1, fixed_iter)
+    if X is None:
+        X = torch.empty_like(packed)
+    if info is None:
+        info = torch.empty(batch * ctypes.sizeof(nn_info_dev), dtype=torch.uint8, device=packed.device)
+    ctx = ctx or default_context(packed.device.index or 0)
+    need = nn_batched_workspace_size(batch, dt)
+    hold = None
+    if ws is None:
+        hold, ws_ptr, ws_bytes = workspace(max(need, 1), packed.device)
+    else:
+        hold, ws_ptr, ws_bytes = ws
+    st = nn_invert_batched(ctx.ptr, ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                           ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(sizes.data_ptr()),
+                           batch, int(max_n), dt, ctypes.byref(prm), ctypes.c_void_p(ws_ptr),
+                           ws_bytes, ctypes.c_void_p(info.data_ptr()))
+    if check and st != NN_OK:
+        raise NNError(st, "nn_invert_batched")
+    X._nn_ws_hold = hold  # keep the workspace alive until the caller syncs
+    return X, info
+
+
+def decode_batched_info(info_bytes):
+    """(iters int32[], status int32[], rms float64[]) from an nn_info_dev buffer."""
+    import numpy as np
+    raw = info_bytes.cpu().numpy().view(np.uint8)
+    rec = np.frombuffer(raw.tobytes(), dtype=np.dtype([("iters", "<i4"), ("status", "<i4"),
+                                                        ("rms", "<f8")]))
+    return rec["iters"].copy(), rec["status"].copy(), rec["rms"].copy()

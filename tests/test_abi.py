@@ -1,0 +1,82 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/nn.h declares, its structs have the sizes the binding assumes, and
+argument errors are reported before anything touches the device."""
+import ctypes
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2212_02406_amd", "libnn.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libnn.so not built")
+
+
+def _nn():
+    from paper_2212_02406_amd import nn
+    return nn
+
+
+def test_exports_every_declared_symbol():
+    nn = _nn()
+    names = nn.header_functions()
+    assert {"nn_create", "nn_destroy", "nn_invert", "nn_solve", "nn_invert_batched",
+            "nn_workspace_size", "nn_status_string"} <= set(names)
+    raw = ctypes.CDLL(LIB)
+    for name in names:
+        assert hasattr(raw, name), name
+
+
+def test_struct_layout():
+    nn = _nn()
+    assert ctypes.sizeof(nn.nn_params) == 32
+    assert nn.nn_info.rms_trace.offset == 48
+    assert ctypes.sizeof(nn.nn_info) == 48 + 8 * nn.NN_TRACE_MAX
+    assert ctypes.sizeof(nn.nn_info_dev) == 16
+
+
+def test_status_strings():
+    nn = _nn()
+    for st in range(-6, 3):
+        assert nn.status_string(st)
+    assert "unknown" in nn.status_string(42)
+
+
+def test_argument_errors_before_launch():
+    nn = _nn()
+    p = nn.make_params()
+    info = nn.nn_info()
+    fake = ctypes.c_void_p(0x1000)
+    # null context / pointers, bad n, bad lda, bad depth: all NN_ERR_ARG
+    assert nn.nn_invert(None, fake, 4, fake, 4, 4, nn.NN_F64, ctypes.byref(p), fake, 1 << 20,
+                        ctypes.byref(info)) == nn.NN_ERR_ARG
+    bad = nn.make_params(depth=0)
+    assert nn.nn_workspace_size(16, nn.NN_F64, ctypes.byref(bad)) == 0
+    bad = nn.make_params(depth=nn.NN_MAX_DEPTH + 1)
+    assert nn.nn_workspace_size(16, nn.NN_F64, ctypes.byref(bad)) == 0
+    bad = nn.make_params(tol=-1.0)
+    assert nn.nn_workspace_size(16, nn.NN_F64, ctypes.byref(bad)) == 0
+    assert nn.nn_workspace_size(0, nn.NN_F64, ctypes.byref(p)) == 0
+    assert nn.nn_workspace_size(16, 9, ctypes.byref(p)) == 0
+
+
+def test_workspace_sizes_grow_with_depth_and_n():
+    nn = _nn()
+    sizes = [nn.nn_workspace_size(512, nn.NN_F64, ctypes.byref(nn.make_params(depth=d)))
+             for d in (1, 2, 3, 4)]
+    assert sizes[0] < sizes[1] < sizes[2] == sizes[3]
+    mat = 512 * 512 * 8
+    assert sizes[0] >= 2 * mat and sizes[2] >= 4 * mat
+    f32 = nn.nn_workspace_size(512, nn.NN_F32, ctypes.byref(nn.make_params()))
+    c128 = nn.nn_workspace_size(512, nn.NN_C128, ctypes.byref(nn.make_params()))
+    assert f32 < sizes[1] < c128
+
+
+def test_create_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    nn = _nn()
+    c = ctypes.c_void_p()
+    assert nn.nn_create(ctypes.byref(c), 0, None) in (nn.NN_ERR_HIP, nn.NN_ERR_ARG)
+    assert nn.nn_create(None, 0, None) == nn.NN_ERR_ARG
