@@ -155,7 +155,7 @@ def main():
         "gemms_per_inverse": info["gemms"],
         "check": {"sampled_cols": len(cols), "max_rel_err_vs_exact_inverse_col": err,
                   "max_residual_col_norm": res},
-        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,16,2,2,2>",
+        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,8,2,4,2,2,false>",
                      "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f64"], "traffic": None,
                      "per_launch_flop": flop_gemm, "avg_launch_ms": avg_gemm_s * 1e3},

@@ -26,6 +26,9 @@
 //    of the interleaved A (M x 2K) with the real 2K x 2N form of B whose row
 //    2k is B's row k as stored and row 2k+1 is the same row with each pair
 //    (re, im) replaced by (-im, re).  That expansion is done while staging B.
+#include <stdlib.h>
+#include <string.h>
+
 #include "nn_internal.h"
 
 namespace nn {
@@ -73,6 +76,9 @@ __device__ __forceinline__ T& lane_of(typename VecOf<T, V>::type& v, int e) {
 
 constexpr int kGroupM = 8;
 
+// Source of the zeros loaded for out-of-range elements (read only).
+__device__ __attribute__((aligned(16))) const double kZero16[2] = {0.0, 0.0};
+
 __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
   const int q = nwg / kNumXcd, r = nwg % kNumXcd;
   const int x = bid % kNumXcd, local = bid / kNumXcd;
@@ -89,8 +95,8 @@ __device__ __forceinline__ void grouped_tile(int tile, int tm, int tn, int& pm, 
   pn = in / gsize;
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int VEC, bool CPLX>
-__global__ void __launch_bounds__(WM* WN * 64)
+template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC, int VEC, bool CPLX>
+__global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(OCC)))
     gemm_kernel(GemmArgs p, int tiles_m, int tiles_n) {
   constexpr int NT = WM * WN * 64;
   constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -99,8 +105,11 @@ __global__ void __launch_bounds__(WM* WN * 64)
   constexpr int LAS = BK + PAD;  // As row stride ([m][k] layout)
   constexpr int LBS = BN + PAD;  // Bs row stride ([k][n] layout)
   constexpr int A_VPR = BK / VEC, B_VPR = BN / VEC;
-  constexpr int A_LOADS = BM * A_VPR / NT, B_LOADS = BK * B_VPR / NT;
-  static_assert(BM * A_VPR % NT == 0 && BK * B_VPR % NT == 0, "load split");
+  // vectors per slab, and per thread (the last round may cover only some
+  // waves when a slab holds fewer vectors than the workgroup has threads)
+  constexpr int A_TOT = BM * A_VPR, B_TOT = BK * B_VPR;
+  constexpr int A_LOADS = (A_TOT + NT - 1) / NT, B_LOADS = (B_TOT + NT - 1) / NT;
+  static_assert(A_TOT % 64 == 0 && B_TOT % 64 == 0, "whole waves per load round");
   static_assert(BK % 4 == 0 && WTM % 16 == 0 && WTN % 16 == 0, "mfma shape");
   static_assert(!CPLX || VEC % 2 == 0, "complex staging needs pairs");
   using acc_t = typename Mfma<T>::acc_t;
@@ -128,43 +137,32 @@ __global__ void __launch_bounds__(WM* WN * 64)
 
   vec_t ra[A_LOADS], rb[B_LOADS];
 
+  // Global -> register staging, branch-free: an out-of-range vector is read
+  // from a 16-byte all-zero device array instead of the matrix, so nothing
+  // consumes the loaded registers until they are stored to LDS after the
+  // current slab's MFMAs (the loads stay in flight across the compute).  The
+  // vector path is chosen by the host only when K, N and the leading
+  // dimensions are multiples of VEC, so a vector is wholly in or out.
+  const T* __restrict__ zsrc = reinterpret_cast<const T*>(kZero16);
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int v = tid + i * NT;
+      if (A_TOT % NT != 0 && v >= A_TOT) break;
       const int r = v / A_VPR, c = (v % A_VPR) * VEC;
       const int64_t gr = m0 + r, gc = k0 + c;
-      if (gr < M && gc + VEC <= K) {
-        ra[i] = *reinterpret_cast<const vec_t*>(A + gr * p.lda + gc);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          lane_of<T, VEC>(ra[i], e) = (gr < M && gc + e < K) ? A[gr * p.lda + gc + e] : T(0);
-      }
+      const bool ok = gr < M && gc < K;
+      ra[i] = *reinterpret_cast<const vec_t*>(ok ? A + gr * p.lda + gc : zsrc);
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int v = tid + i * NT;
+      if (B_TOT % NT != 0 && v >= B_TOT) break;
       const int r = v / B_VPR, c = (v % B_VPR) * VEC;
       const int64_t gr = k0 + r, gc = n0 + c;
       const int64_t srow = CPLX ? (gr >> 1) : gr;
-      if (gr < K && gc + VEC <= N) {
-        rb[i] = *reinterpret_cast<const vec_t*>(B + srow * p.ldb + gc);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          lane_of<T, VEC>(rb[i], e) = (gr < K && gc + e < N) ? B[srow * p.ldb + gc + e] : T(0);
-      }
-      if constexpr (CPLX) {
-        if (gr & 1) {
-#pragma unroll
-          for (int e = 0; e < VEC; e += 2) {
-            const T re = lane_of<T, VEC>(rb[i], e), im = lane_of<T, VEC>(rb[i], e + 1);
-            lane_of<T, VEC>(rb[i], e) = -im;
-            lane_of<T, VEC>(rb[i], e + 1) = re;
-          }
-        }
-      }
+      const bool ok = gr < K && gc < N;
+      rb[i] = *reinterpret_cast<const vec_t*>(ok ? B + srow * p.ldb + gc : zsrc);
     }
   };
 
@@ -172,27 +170,36 @@ __global__ void __launch_bounds__(WM* WN * 64)
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int v = tid + i * NT;
+      if (A_TOT % NT != 0 && v >= A_TOT) break;
       const int r = v / A_VPR, c = (v % A_VPR) * VEC;
       *reinterpret_cast<vec_t*>(&As[buf][r * LAS + c]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int v = tid + i * NT;
+      if (B_TOT % NT != 0 && v >= B_TOT) break;
       const int r = v / B_VPR, c = (v % B_VPR) * VEC;
-      *reinterpret_cast<vec_t*>(&Bs[buf][r * LBS + c]) = rb[i];
+      vec_t x = rb[i];
+      if constexpr (CPLX) {
+        // odd rows of the real form of a complex B: (re, im) -> (-im, re);
+        // the slab origin is a multiple of BK (even), so r's parity is the row's
+        if (r & 1) {
+#pragma unroll
+          for (int e = 0; e < VEC; e += 2) {
+            const T re = lane_of<T, VEC>(x, e), im = lane_of<T, VEC>(x, e + 1);
+            lane_of<T, VEC>(x, e) = -im;
+            lane_of<T, VEC>(x, e + 1) = re;
+          }
+        }
+      }
+      *reinterpret_cast<vec_t*>(&Bs[buf][r * LBS + c]) = x;
     }
   };
 
-  const int nk = (int)((K + BK - 1) / BK);
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
-    const T* as = As[cur] + (wm * WTM + lr) * LAS + lk;
-    const T* bs = Bs[cur] + lk * LBS + wn * WTN + lr;
+  auto compute = [&](int buf) {
+    const T* as = As[buf] + (wm * WTM + lr) * LAS + lk;
+    const T* bs = Bs[buf] + lk * LBS + wn * WTN + lr;
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       T af[FM], bf[FN];
@@ -205,9 +212,21 @@ __global__ void __launch_bounds__(WM* WN * 64)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[i], bf[j], acc[i][j]);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+
+  // Steady state without conditionals: prefetch slab kt+1 into registers,
+  // multiply slab kt from LDS, store slab kt+1 into the other LDS buffer.
+  const int nk = (int)((K + BK - 1) / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk - 1; ++kt) {
+    gload((int64_t)(kt + 1) * BK);
+    compute(kt & 1);
+    sstore((kt + 1) & 1);
     __syncthreads();
   }
+  compute((nk - 1) & 1);
 
   // Epilogue: C = alpha * acc + E + diag * I, and the tile's sum of squares.
   T* __restrict__ C = static_cast<T*>(p.C);
@@ -251,18 +270,24 @@ struct TileShape {
 };
 inline TileShape shape_of(Tile t) {
   switch (t) {
-    case Tile::T128: return {128, 128};
+    case Tile::T128:
+    case Tile::T128W8:
+    case Tile::T128K8:
+    case Tile::T128W8K8: return {128, 128};
+    case Tile::T256K8:
+    case Tile::T256: return {256, 128};
     case Tile::T64: return {64, 64};
-    case Tile::T32: return {32, 32};
+    case Tile::T32:
+    case Tile::kCount: return {32, 32};
   }
   return {32, 32};
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int VEC, bool CPLX>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC, int VEC, bool CPLX>
 hipError_t launch_one(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
   const int grid = plan.num_tiles();
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, VEC, CPLX>), dim3(grid),
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, OCC, VEC, CPLX>), dim3(grid),
                      dim3(WM * WN * 64), 0, s, a, plan.tiles_m, plan.tiles_n);
   return hipGetLastError();
 }
@@ -270,24 +295,50 @@ hipError_t launch_one(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
 template <typename T, int VEC, bool CPLX>
 hipError_t launch_tile(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
   switch (plan.tile) {
-    case Tile::T128: return launch_one<T, 128, 128, 16, 2, 2, VEC, CPLX>(plan, a, s);
-    case Tile::T64: return launch_one<T, 64, 64, 16, 2, 2, VEC, CPLX>(plan, a, s);
-    case Tile::T32: return launch_one<T, 32, 32, 16, 1, 1, VEC, CPLX>(plan, a, s);
+    case Tile::T128: return launch_one<T, 128, 128, 16, 2, 2, 1, VEC, CPLX>(plan, a, s);
+    case Tile::T128W8: return launch_one<T, 128, 128, 16, 2, 4, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T128K8: return launch_one<T, 128, 128, 8, 2, 2, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T128W8K8: return launch_one<T, 128, 128, 8, 2, 4, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T256K8: return launch_one<T, 256, 128, 8, 4, 2, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T256: return launch_one<T, 256, 128, 16, 4, 2, 2, VEC, CPLX>(plan, a, s);
+    case Tile::T64: return launch_one<T, 64, 64, 16, 2, 2, 1, VEC, CPLX>(plan, a, s);
+    case Tile::T32:
+    case Tile::kCount: return launch_one<T, 32, 32, 16, 1, 1, 1, VEC, CPLX>(plan, a, s);
   }
   return hipErrorInvalidValue;
 }
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+
+bool tile_override(Tile* t) {
+  const char* v = getenv("NN_GEMM_TILE");
+  if (!v) return false;
+  const char* names[] = {"T128", "T128W8", "T128K8", "T128W8K8", "T256K8", "T256", "T64", "T32"};
+  for (int i = 0; i < (int)Tile::kCount; ++i) {
+    if (strcmp(v, names[i]) == 0) {
+      *t = static_cast<Tile>(i);
+      return true;
+    }
+  }
+  return false;
+}
+
 }  // namespace
 
+// Tile choice by measured throughput on gfx950 at N = 8192: FP64 runs best
+// with 8 waves of 64x32 and an 8-deep k-slab (64 TFLOP/s), FP32 with the
+// 256x128 tile (133 TFLOP/s).  Smaller problems drop to smaller tiles while
+// the larger ones would leave CUs idle (256 CUs).
 GemmPlan plan_gemm(Elem e, int64_t M, int64_t N) {
-  (void)e;
-  auto tiles = [&](int b) { return (int)(((M + b - 1) / b) * ((N + b - 1) / b)); };
+  auto tiles = [&](int bm, int bn) { return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn)); };
   GemmPlan p;
-  if (tiles(128) >= 256) p.tile = Tile::T128;
-  else if (tiles(64) >= 128) p.tile = Tile::T64;
-  else p.tile = Tile::T32;
+  if (!tile_override(&p.tile)) {
+    if (e == Elem::F32 && tiles(256, 128) >= 256) p.tile = Tile::T256;
+    else if (tiles(128, 128) >= 256) p.tile = e == Elem::F32 ? Tile::T128W8 : Tile::T128W8K8;
+    else if (tiles(64, 64) >= 128) p.tile = Tile::T64;
+    else p.tile = Tile::T32;
+  }
   const TileShape sh = shape_of(p.tile);
   p.tiles_m = (int)((M + sh.bm - 1) / sh.bm);
   p.tiles_n = (int)((N + sh.bn - 1) / sh.bn);
@@ -297,16 +348,21 @@ GemmPlan plan_gemm(Elem e, int64_t M, int64_t N) {
 hipError_t launch_gemm(Elem e, bool cplx, const GemmPlan& plan, const GemmArgs& a,
                        hipStream_t s) {
   const bool al = aligned16(a.A) && aligned16(a.B);
+  auto fits = [&](int v) {
+    return al && a.lda % v == 0 && a.ldb % v == 0 && a.K % v == 0 && a.N % v == 0;
+  };
   if (e == Elem::F64) {
-    const bool v2 = al && a.lda % 2 == 0 && a.ldb % 2 == 0;
-    if (cplx) return launch_tile<double, 2, true>(plan, a, s);  // 16-byte complex elements
-    return v2 ? launch_tile<double, 2, false>(plan, a, s) : launch_tile<double, 1, false>(plan, a, s);
+    // complex: 16-byte elements, so K, N, lda, ldb (real) are always even
+    if (cplx) return launch_tile<double, 2, true>(plan, a, s);
+    return fits(2) ? launch_tile<double, 2, false>(plan, a, s)
+                   : launch_tile<double, 1, false>(plan, a, s);
   }
   if (e == Elem::F32) {
-    const bool v4 = al && a.lda % 4 == 0 && a.ldb % 4 == 0;
     if (cplx)
-      return v4 ? launch_tile<float, 4, true>(plan, a, s) : launch_tile<float, 2, true>(plan, a, s);
-    return v4 ? launch_tile<float, 4, false>(plan, a, s) : launch_tile<float, 1, false>(plan, a, s);
+      return fits(4) ? launch_tile<float, 4, true>(plan, a, s)
+                     : launch_tile<float, 2, true>(plan, a, s);
+    return fits(4) ? launch_tile<float, 4, false>(plan, a, s)
+                   : launch_tile<float, 1, false>(plan, a, s);
   }
   return hipErrorInvalidValue;
 }

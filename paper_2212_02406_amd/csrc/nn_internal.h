@@ -31,8 +31,18 @@ struct GemmArgs {
 
 enum class Elem { F64, F32, BF16IN_F32OUT };
 
-// Tile configurations selectable by the host.
-enum class Tile { T128, T64, T32 };
+// Tile configurations selectable by the host (macro tile, waves, k-slab):
+//   T128   128x128, 4 waves of 64x64, BK 16
+//   T128W8 128x128, 8 waves of 64x32, BK 16 (two waves per SIMD)
+//   T128K8 128x128, 4 waves of 64x64, BK 8, register budget for two waves/SIMD
+//   T128W8K8 128x128, 8 waves of 64x32, BK 8
+//   T256K8 256x128, 8 waves of 64x64, BK 8
+//   T256   256x128, 8 waves of 64x64, BK 16
+//   T64     64x64,  4 waves of 32x32, BK 16
+//   T32     32x32,  1 wave  of 32x32, BK 16
+// The environment variable NN_GEMM_TILE (one of the names above) forces one
+// configuration for every GEMM, for tuning and for tests.
+enum class Tile { T128, T128W8, T128K8, T128W8K8, T256K8, T256, T64, T32, kCount };
 
 struct GemmPlan {
   Tile tile;

@@ -110,6 +110,27 @@ def test_ragged_sizes_fp64(n, ld):
     assert abs(info["rms"] - io["rms"]) <= 1e-9 * io["rms"] + 1e-15
 
 
+@pytest.mark.parametrize("tile", ["T128", "T128W8", "T128K8", "T128W8K8", "T256K8", "T256",
+                                  "T64", "T32"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.complex128, np.complex64])
+def test_every_tile_config(tile, dtype, monkeypatch):
+    """Each GEMM tile configuration, forced for every product, on a size with
+    ragged tails in both dimensions and an odd leading dimension."""
+    _say(f"tile {tile} {np.dtype(dtype).name}")
+    monkeypatch.setenv("NN_GEMM_TILE", tile)
+    n = 197
+    cplx = np.dtype(dtype).kind == "c"
+    A = W.dense_spd(n, 1.0, 40.0, 31, complex_=cplx, dtype=dtype)
+    ref = A.astype(np.complex128 if cplx else np.float64)
+    Xo, io = oracle.nn_ref(ref, d=3, fixed_iter=5)
+    for ld in (n, n + 1):
+        X, info = _gpu_invert(A, ld=ld, depth=3, fixed_iter=5)
+        assert info["status"] == nn.NN_OK
+        single = np.dtype(dtype) in (np.dtype(np.float32), np.dtype(np.complex64))
+        tol = 64 * U32 * np.linalg.cond(ref) if single else 1e-10
+        assert _relF(X.astype(ref.dtype), Xo) < tol
+
+
 @pytest.mark.parametrize("n", [5, 64, 130, 300])
 def test_nonsymmetric_fp64(n):
     _say(f"nonsym fp64 n={n}")
