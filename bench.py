@@ -112,8 +112,8 @@ def cpu_baseline(A_h, depth, iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the sharded design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "this library runs on one GPU: --gpus must be 1; "
+                                   "more GPUs are not supported"}))
         sys.exit(2)
     import numpy as np
     import torch
