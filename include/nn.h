@@ -180,6 +180,25 @@ nn_status nn_invert_batched(nn_ctx* ctx, const void* A_packed, void* X_packed,
                             int32_t max_n, nn_dtype dtype, const nn_params* params,
                             void* ws, size_t ws_bytes, nn_info_dev* per_matrix);
 
+/* Autotune nn_invert_batched for this batch: time each candidate kernel
+ * configuration (size up to which a matrix gets one wave instead of a whole
+ * workgroup: 0, 8, 16, 32; workgroups per CU: 1, 2, 4, ... as LDS allows) on
+ * the given arguments, three replays each, and keep the fastest in the
+ * context for later calls with the same dtype and max_n.  Arguments as for
+ * nn_invert_batched; X_packed is overwritten.  *best_ms (optional) receives
+ * the best replay time.  Blocks until done. */
+nn_status nn_batched_autotune(nn_ctx* ctx, const void* A_packed, void* X_packed,
+                              const int64_t* offsets, const int32_t* sizes, int32_t batch,
+                              int32_t max_n, nn_dtype dtype, const nn_params* params,
+                              void* ws, size_t ws_bytes, float* best_ms);
+
+/* Read / set the batched kernel configuration the context uses for (dtype,
+ * max_n): wave_max_k in [0, 32], wg_per_cu in [1, 8]. */
+nn_status nn_batched_get_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
+                                int32_t* wave_max_k, int32_t* wg_per_cu);
+nn_status nn_batched_set_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
+                                int32_t wave_max_k, int32_t wg_per_cu);
+
 /* Static description of a status code. */
 const char* nn_status_string(nn_status status);
 

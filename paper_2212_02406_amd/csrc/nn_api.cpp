@@ -23,16 +23,6 @@
 
 #include "nn_internal.h"
 
-constexpr int kTimedGemms = 1024;
-
-struct nn_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  double* host = nullptr;  // pinned read-back slots
-  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
-  hipEvent_t* ev_gemm = nullptr;  // 2 * kTimedGemms events, created on first timed call
-};
-
 namespace nn {
 namespace {
 
@@ -337,6 +327,9 @@ nn_status nn_create(nn_ctx** out, int device, void* stream) {
   if (!c) return NN_ERR_HIP;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * kHostSlots,
                     hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess) {
@@ -356,6 +349,9 @@ void nn_destroy(nn_ctx* c) {
     for (int i = 0; i < 2 * kTimedGemms; ++i) (void)hipEventDestroy(c->ev_gemm[i]);
     delete[] c->ev_gemm;
   }
+  if (c->bgraph.exec) (void)hipGraphExecDestroy(c->bgraph.exec);
+  if (c->bgraph.graph) (void)hipGraphDestroy(c->bgraph.graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

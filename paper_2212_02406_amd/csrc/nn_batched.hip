@@ -1,0 +1,496 @@
+// nn_batched.hip — many small NN inversions in one persistent launch (gfx950).
+//
+// Workload: the massive-MIMO regularised Gram matrices G = H^H H + s^2 I that
+// motivate the Chebyshev-Neumann discussion after Corollary 4 of the paper
+// (arXiv 2212.02406): thousands of Hermitian PD matrices of uneven sizes
+// (K <= 64), a fixed number of nests at depth d (Sec. II-D Theorem).
+//
+// Structure:
+//  * plan kernel (one block): counting sort of the matrices by size, largest
+//    first (longest-processing-time order), the split into "group" matrices
+//    (a whole 4-wave workgroup each) and "wave" matrices (K <= wave_max_k,
+//    one wave each, four per work item), and the reset of the work counter.
+//  * persistent kernel: each workgroup pops work items from the counter
+//    until the queue is empty (every wave reaches that exit).  A matrix lives
+//    entirely in LDS (buffers G, X, R, U) for all its nests; global memory is
+//    touched only to load G and store X and the per-matrix info.
+//  * every product is an LDS-to-register GEMM on v_mfma_f32_16x16x4_f32; a
+//    complex product is the real product of the interleaved left factor with
+//    the real 2K x 2K form of the right factor, expanded on read (row 2k is
+//    row k of B, row 2k+1 is that row with (re, im) -> (-im, re)).  The whole
+//    product stays in registers until the group barrier, so the output may
+//    overwrite an input buffer (X' = X + X U is written over X).
+//  * results depend only on the matrix and its size class: block-to-wave
+//    assignment and summation orders are fixed, so a matrix gives the same
+//    bits alone or in any batch.
+#include <math.h>
+
+#include "nn_internal.h"
+
+namespace nn {
+namespace {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxN = 64;
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 8;  // 16x16 output blocks per wave (K = 64 complex over 4 waves)
+
+struct BatchHdr {
+  int32_t counter;
+  int32_t n_large;
+  int32_t n_small;
+  int32_t n_items;
+  int32_t bad;
+  int32_t pad[3];
+};
+
+// LDS layout of a K x K matrix: real columns padded to a multiple of 16 plus
+// 4 (row stride ld, a multiple of 4 floats so 16-byte reads stay aligned;
+// ld = 4 or 20 mod 32 makes the 8-lane groups of those reads hit distinct
+// banks), rows padded to a multiple of 16.  The padding is zero, so the
+// MFMA loop needs no masks.
+__device__ __host__ __forceinline__ int pad16(int x) { return (x + 15) & ~15; }
+__device__ __host__ __forceinline__ int lds_ld(int K, bool cplx) {
+  return pad16(cplx ? 2 * K : K) + 4;
+}
+__device__ __host__ __forceinline__ int lds_buf(int K, bool cplx) {
+  return pad16(K) * lds_ld(K, cplx);
+}
+
+// Dynamic LDS of the persistent kernel (matrix buffers) and the per-group
+// reduction scratch.  Everything below addresses LDS through these arrays and
+// integer offsets, so the accesses compile to ds_read/ds_write.
+extern __shared__ __attribute__((aligned(16))) float smem[];
+__shared__ double s_red[4][8 + 2 * kMaxN];
+
+struct Group {
+  int gw;      // wave index inside the group
+  int G;       // waves in the group (4 or 1)
+  int lane;
+  int gtid;    // thread index inside the group
+  int redrow;  // row of s_red this group uses
+  bool whole;  // the group is the whole workgroup
+  __device__ __forceinline__ void sync() const {
+    if (whole) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+// Operands of one k-group (16 real k) for NB output blocks.
+template <bool CPLX, int NB>
+struct KFrag {
+  f4_t a[NB];
+  f4_t b[NB];  // complex: (p0.x, p0.y, p1.x, p1.y); real: 4 rows of B
+};
+
+template <bool CPLX, int NB>
+__device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB>& f, const int* aoff, const int* boff,
+                                            int j, int ld) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    f.a[i] = *reinterpret_cast<const f4_t*>(&smem[aoff[i] + 16 * j]);
+    if constexpr (CPLX) {
+      const int o = boff[i] + 8 * j * ld;
+      const f2_t p0 = *reinterpret_cast<const f2_t*>(&smem[o]);
+      const f2_t p1 = *reinterpret_cast<const f2_t*>(&smem[o + ld]);
+      f.b[i] = f4_t{p0.x, p0.y, p1.x, p1.y};
+    } else {
+      const int o = boff[i] + 16 * j * ld;
+      f.b[i] = f4_t{smem[o], smem[o + ld], smem[o + 2 * ld], smem[o + 3 * ld]};
+    }
+  }
+}
+
+template <bool CPLX, int NB>
+__device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB>& f, const bool* even) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    float b0, b1, b2, b3;
+    if constexpr (CPLX) {
+      // expanded rows 2 kc, 2 kc + 1 of two complex rows kc0, kc0 + 1
+      const bool ev = even[i];
+      b0 = ev ? f.b[i].x : f.b[i].y;
+      b1 = ev ? -f.b[i].y : f.b[i].x;
+      b2 = ev ? f.b[i].z : f.b[i].w;
+      b3 = ev ? -f.b[i].w : f.b[i].z;
+    } else {
+      b0 = f.b[i].x;
+      b1 = f.b[i].y;
+      b2 = f.b[i].z;
+      b3 = f.b[i].w;
+    }
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].x, b0, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].y, b1, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].z, b2, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].w, b3, acc[i], 0, 0, 0);
+  }
+}
+
+// C = alpha * A B + E + diag * I on K x K matrices held in LDS at float
+// offsets A, B, E (E < 0: none), C, row stride ld, zero padding as above.
+// C may alias A, B or E.  If ss is non-null the group's sum of |C_ij|^2 is
+// returned through it.  NB = blocks per wave, the same for every wave of the
+// group; a wave's blocks past the last one recompute that block and do not
+// store it.
+//
+// k-assignment: in k-group j (16 real k) MFMA step q takes, for the lanes of
+// quarter lk, k = 16 j + 4 lk + q.  Each step still covers four distinct k, and
+// a lane's four A values of the group are contiguous (one 16-byte read).  For
+// a complex B the four k are the rows 2 kc, 2 kc + 1 of two complex rows, whose
+// expanded entries come from one 8-byte (re, im) read each.  All operand reads
+// of a k-group are issued before its MFMAs.
+template <bool CPLX, int NB>
+__device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, int ld,
+                                            float alpha, float diag, const Group& g,
+                                            double* ss) {
+  const int cols = CPLX ? 2 * K : K;
+  const int nbm = (K + 15) >> 4, nbn = (cols + 15) >> 4, nb = nbm * nbn;
+  const int first = g.gw * NB;
+  const int lr = g.lane & 15, lk = g.lane >> 4;
+  f4_t acc[NB];
+  int aoff[NB], boff[NB], bm_[NB], bn_[NB];
+  bool even[NB], live[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    acc[i] = f4_t{};
+    live[i] = first + i < nb;
+    const int b = live[i] ? first + i : nb - 1;
+    bm_[i] = b / nbn;
+    bn_[i] = b - bm_[i] * nbn;
+    const int n = bn_[i] * 16 + lr;
+    aoff[i] = A + (bm_[i] * 16 + lr) * ld + 4 * lk;
+    if constexpr (CPLX) {
+      boff[i] = B + (2 * lk) * ld + (n & ~1);
+      even[i] = !(n & 1);
+    } else {
+      boff[i] = B + (4 * lk) * ld + n;
+      even[i] = true;
+    }
+  }
+  const int kgroups = nbn;  // padded real inner dimension / 16
+  for (int j = 0; j < kgroups; ++j) {
+    KFrag<CPLX, NB> f;
+    load_kgroup<CPLX, NB>(f, aoff, boff, j, ld);  // all operand reads of the group first
+    mma_kgroup<CPLX, NB>(acc, f, even);
+  }
+  // Epilogue in registers (rows 4 (lane/16) + t of each block, FP32 layout).
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int n = bn_[i] * 16 + lr;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int m = bm_[i] * 16 + 4 * lk + t;
+      if (live[i] && m < K && n < cols) {
+        float v = alpha * acc[i][t];
+        if (E >= 0) v += smem[E + m * ld + n];
+        if (CPLX ? (n == 2 * m) : (n == m)) v += diag;
+        acc[i][t] = v;
+        s += (double)v * (double)v;
+      }
+    }
+  }
+  g.sync();  // every read of A, B, E is done
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int n = bn_[i] * 16 + lr;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int m = bm_[i] * 16 + 4 * lk + t;
+      if (live[i] && m < K && n < cols) smem[C + m * ld + n] = acc[i][t];
+    }
+  }
+  if (ss) {
+    s = wave_sum(s);
+    if (g.G > 1) {
+      if (g.lane == 0) s_red[g.redrow][g.gw] = s;
+      g.sync();
+      double t = 0.0;
+      for (int w = 0; w < g.G; ++w) t += s_red[g.redrow][w];
+      s = t;
+    }
+    *ss = s;
+  }
+  g.sync();
+}
+
+// Blocks per wave for a K x K product over G waves, rounded up to 1, 2, 4 or
+// 8 (the kernel is instantiated for those counts only).
+__device__ __forceinline__ int blocks_per_wave(int K, bool cplx, int G) {
+  const int cols = cplx ? 2 * K : K;
+  const int nb = ((K + 15) >> 4) * ((cols + 15) >> 4);
+  const int per = (nb + G - 1) / G;
+  return per <= 1 ? 1 : per <= 2 ? 2 : per <= 4 ? 4 : 8;
+}
+
+// The whole NN run for one matrix: load, start iterate, `iters` nests of
+// depth d, final residual, store.
+template <bool CPLX, int NB>
+__device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, int depth, int x0,
+                                           int iters,
+                           int buf, int bufstride, const Group& g, nn_info_dev* info) {
+  const int cols = CPLX ? 2 * K : K;
+  const int ld = lds_ld(K, CPLX);
+  const int Gs = buf, Xs = buf + bufstride, Rs = buf + 2 * bufstride, Us = buf + 3 * bufstride;
+  double* red = s_red[g.redrow];
+  const int nthr = g.G * 64;
+  if ((K & 15) || (cols & 15)) {  // ragged size: the padding must read as zero
+    const int nb = lds_buf(K, CPLX);
+    for (int q = 0; q < 4; ++q)
+      for (int e = g.gtid; e < nb; e += nthr) smem[buf + q * bufstride + e] = 0.f;
+    g.sync();
+  }
+  for (int e = g.gtid; e < K * cols; e += nthr) {
+    const int r = e / cols, c = e - r * cols;
+    smem[Gs + r * ld + c] = Ag[e];
+  }
+  g.sync();
+  // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G.
+  double den;
+  if (x0 == NN_X0_TRANSPOSE) {
+    if (g.gtid < 2 * K) {
+      const bool row = g.gtid < K;
+      const int i = row ? g.gtid : g.gtid - K;
+      double s = 0.0;
+      for (int j = 0; j < K; ++j) {
+        const int r = row ? i : j, c = row ? j : i;
+        if constexpr (CPLX) {
+          const double re = smem[Gs + r * ld + 2 * c], im = smem[Gs + r * ld + 2 * c + 1];
+          s += sqrt(re * re + im * im);
+        } else {
+          s += fabs((double)smem[Gs + r * ld + c]);
+        }
+      }
+      red[8 + g.gtid] = s;
+    }
+    g.sync();
+    double n1 = 0.0, ninf = 0.0;
+    bool bad = false;
+    for (int i = 0; i < K; ++i) {
+      const double r = red[8 + i], c = red[8 + K + i];
+      bad |= !isfinite(r) || !isfinite(c);
+      ninf = r > ninf ? r : ninf;
+      n1 = c > n1 ? c : n1;
+    }
+    den = bad ? NAN : n1 * ninf;
+  } else {
+    double t = 0.0;
+    for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + (CPLX ? 2 * i : i)];
+    den = t;
+  }
+  const bool den_ok = isfinite(den) && den > 0.0;
+  const float s = (float)(1.0 / den);
+  g.sync();
+  for (int e = g.gtid; e < K * cols; e += nthr) {
+    const int r = e / cols, c = e - r * cols;
+    float v;
+    if (x0 == NN_X0_TRANSPOSE) {
+      if constexpr (CPLX) {
+        const int j = c >> 1;  // X[r][j] = conj(G[j][r]) * s
+        v = (c & 1) ? -smem[Gs + j * ld + 2 * r + 1] * s : smem[Gs + j * ld + 2 * r] * s;
+      } else {
+        v = smem[Gs + c * ld + r] * s;
+      }
+    } else {
+      v = (CPLX ? (c == 2 * r) : (c == r)) ? s : 0.f;
+    }
+    smem[Xs + r * ld + c] = v;
+  }
+  g.sync();
+  for (int it = 0; it < iters; ++it) {
+    lds_gemm_nb<CPLX, NB>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, nullptr);  // R = I - G X
+    int U = Rs;
+    for (int m = 1; m < depth; ++m) {  // U_{m+1} = R + R U_m
+      lds_gemm_nb<CPLX, NB>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr);
+      U = Us;
+    }
+    lds_gemm_nb<CPLX, NB>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
+  }
+  double ss = 0.0;
+  lds_gemm_nb<CPLX, NB>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, &ss);
+  const double rms = sqrt(ss / (double)K);
+  for (int e = g.gtid; e < K * cols; e += nthr) {
+    const int r = e / cols, c = e - r * cols;
+    Xg[e] = smem[Xs + r * ld + c];
+  }
+  if (info && g.gtid == 0) {
+    nn_info_dev d;
+    d.iters = iters;
+    d.rms = rms;
+    d.status = !den_ok ? (isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE)
+                       : (isfinite(rms) ? NN_OK : NN_ERR_NONFINITE);
+    *info = d;
+  }
+  g.sync();
+}
+
+__global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int batch, int max_n,
+                                                     int wave_max_k, BatchHdr* hdr, int32_t* perm,
+                                                     nn_info_dev* info) {
+  __shared__ int cnt[kMaxN + 1], start[kMaxN + 1], fill[kMaxN + 1];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t <= kMaxN) {
+    cnt[t] = 0;
+    fill[t] = 0;
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int b = t; b < batch; b += blockDim.x) {
+    int k = sizes[b];
+    if (k < 1 || k > max_n) {
+      k = 0;
+      bad = 1;
+      if (info) {
+        nn_info_dev d;
+        d.iters = 0;
+        d.status = NN_ERR_ARG;
+        d.rms = NAN;
+        info[b] = d;
+      }
+    }
+    atomicAdd(&cnt[k], 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int k = kMaxN; k >= 1; --k) {
+      start[k] = acc;
+      acc += cnt[k];
+    }
+    start[0] = acc;
+    int large = 0;
+    for (int k = wave_max_k + 1; k <= kMaxN; ++k) large += cnt[k];
+    const int small = batch - cnt[0] - large;
+    hdr->counter = 0;
+    hdr->n_large = large;
+    hdr->n_small = small;
+    hdr->n_items = large + (small + 3) / 4;
+    hdr->bad = bad;
+  }
+  __syncthreads();
+  for (int b = t; b < batch; b += blockDim.x) {
+    int k = sizes[b];
+    if (k < 1 || k > max_n) k = 0;
+    perm[start[k] + atomicAdd(&fill[k], 1)] = b;
+  }
+}
+
+template <bool CPLX>
+__global__ void __launch_bounds__(kThreads) batched_nn(const float* A, float* X,
+                                                       const int64_t* offsets,
+                                                       const int32_t* sizes, const int32_t* perm,
+                                                       BatchHdr* hdr, int max_n, int wave_max_k,
+                                                       int depth, int x0, int iters,
+                                                       nn_info_dev* info) {
+  __shared__ int item_s;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int cm = CPLX ? 2 : 1;
+  const int big_stride = lds_buf(max_n, CPLX);
+  const int wk = wave_max_k > 0 ? wave_max_k : 1;
+  const int wave_stride = lds_buf(wk, CPLX);
+  const int n_items = hdr->n_items, n_large = hdr->n_large, n_small = hdr->n_small;
+  for (;;) {
+    if (tid == 0) item_s = atomicAdd(&hdr->counter, 1);
+    __syncthreads();
+    const int item = item_s;
+    __syncthreads();
+    if (item >= n_items) break;
+    if (item < n_large) {
+      const int b = perm[item];
+      const Group g{wave, 4, lane, tid, 0, true};
+      const int64_t off = offsets[b] * cm;
+      const int K = sizes[b];
+      nn_info_dev* inf = info ? info + b : nullptr;
+      switch (blocks_per_wave(K, CPLX, 4)) {
+        case 1: invert_one<CPLX, 1>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
+        case 2: invert_one<CPLX, 2>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
+        case 4: invert_one<CPLX, 4>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
+        default: invert_one<CPLX, 8>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
+      }
+    } else {
+      const int idx = n_large + 4 * (item - n_large) + wave;
+      if (idx < n_large + n_small) {
+        const int b = perm[idx];
+        const Group g{0, 1, lane, lane, wave, false};
+        const int64_t off = offsets[b] * cm;
+        const int K = sizes[b];
+        const int base = wave * 4 * wave_stride;
+        nn_info_dev* inf = info ? info + b : nullptr;
+        switch (blocks_per_wave(K, CPLX, 1)) {
+          case 1: invert_one<CPLX, 1>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
+          case 2: invert_one<CPLX, 2>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
+          case 4: invert_one<CPLX, 4>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
+          default: invert_one<CPLX, 8>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+size_t lds_bytes(bool cplx, int max_n, int wave_max_k) {
+  const size_t big = 4 * (size_t)lds_buf(max_n, cplx);
+  const int wk = wave_max_k > 0 ? wave_max_k : 1;
+  const size_t small = 16 * (size_t)lds_buf(wk, cplx);
+  return sizeof(float) * (big > small ? big : small);
+}
+
+}  // namespace
+
+size_t batched_ws_bytes(int32_t batch) { return 256 + ((size_t)batch * 4 + 255) / 256 * 256; }
+
+hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* offsets,
+                          const int32_t* sizes, int32_t batch, int32_t max_n, int depth, int x0,
+                          int iters, int wave_max_k, void* ws, nn_info_dev* info, int grid,
+                          hipStream_t s) {
+  BatchHdr* hdr = static_cast<BatchHdr*>(ws);
+  int32_t* perm = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
+  const bool cplx = dt == NN_C64;
+  if (wave_max_k > max_n) wave_max_k = max_n;
+  hipLaunchKernelGGL(batched_plan, dim3(1), dim3(1024), 0, s, sizes, batch, max_n, wave_max_k,
+                     hdr, perm, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = lds_bytes(cplx, max_n, wave_max_k);
+  if (cplx) {
+    hipLaunchKernelGGL(batched_nn<true>, dim3(grid), dim3(kThreads), lds, s,
+                       static_cast<const float*>(A), static_cast<float*>(X), offsets, sizes, perm,
+                       hdr, max_n, wave_max_k, depth, x0, iters, info);
+  } else {
+    hipLaunchKernelGGL(batched_nn<false>, dim3(grid), dim3(kThreads), lds, s,
+                       static_cast<const float*>(A), static_cast<float*>(X), offsets, sizes, perm,
+                       hdr, max_n, wave_max_k, depth, x0, iters, info);
+  }
+  return hipGetLastError();
+}
+
+hipError_t batched_allow_lds() {
+  const int lim = 150 * 1024;  // dynamic part; the kernels' static LDS is under 10 KB
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_nn<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_nn<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k) {
+  if (wave_max_k > max_n) wave_max_k = max_n;
+  return lds_bytes(dt == NN_C64, max_n, wave_max_k);
+}
+
+}  // namespace nn

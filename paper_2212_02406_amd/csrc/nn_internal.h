@@ -91,10 +91,14 @@ hipError_t launch_cast_f32_bf16(const float* src, int64_t lds, uint16_t* dst, in
 hipError_t launch_sumsq(const void* src, bool f64, int64_t ld, int64_t rows, int64_t cols,
                         double* part, double* out, hipStream_t s);
 
-// Batched persistent kernel.
+// Batched persistent path: plan kernel + persistent kernel on stream s.
+// Matrices of size <= wave_max_k (<= 32) get one wave each; grid workgroups.
+size_t batched_ws_bytes(int32_t batch);
+size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k);
+hipError_t batched_allow_lds();  // raise the dynamic LDS limit (call outside capture)
 hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* offsets,
-                          const int32_t* sizes, int32_t batch, int32_t max_n, int depth,
-                          int x0, int iters, int32_t* queue, nn_info_dev* info,
+                          const int32_t* sizes, int32_t batch, int32_t max_n, int depth, int x0,
+                          int iters, int wave_max_k, void* ws, nn_info_dev* info, int grid,
                           hipStream_t s);
 
 inline size_t elem_size(nn_dtype d) {
@@ -109,4 +113,40 @@ inline size_t elem_size(nn_dtype d) {
 inline bool is_complex(nn_dtype d) { return d == NN_C64 || d == NN_C128; }
 inline bool is_double(nn_dtype d) { return d == NN_F64 || d == NN_C128; }
 
+// Tuned configuration of the batched kernel for one (dtype, max_n).
+struct BatchedTune {
+  int dtype = -1, max_n = 0;
+  int wave_max_k = 16;
+  int wg_per_cu = 1;
+};
+
+// The instantiated graph of the last batched call and its arguments.
+struct BatchedGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* A = nullptr;
+  void* X = nullptr;
+  const int64_t* offsets = nullptr;
+  const int32_t* sizes = nullptr;
+  void* ws = nullptr;
+  nn_info_dev* info = nullptr;
+  int32_t batch = 0, max_n = 0;
+  int dtype = -1, depth = 0, x0 = 0, iters = 0, wave_max_k = 0, grid = 0;
+};
+
 }  // namespace nn
+
+constexpr int kTimedGemms = 1024;
+constexpr int kTuneSlots = 8;
+
+struct nn_ctx {
+  int device = 0;
+  int num_cus = 256;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  double* host = nullptr;            // pinned read-back slots
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  hipEvent_t* ev_gemm = nullptr;  // 2 * kTimedGemms events, created on first timed call
+  nn::BatchedTune tune[kTuneSlots];
+  nn::BatchedGraph bgraph;
+};

@@ -15,7 +15,7 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnn.so")
+LIB_PATH = os.environ.get("NN_LIBRARY") or os.path.join(_HERE, "libnn.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "nn.h")
 
 if not os.path.exists(LIB_PATH):
@@ -77,6 +77,11 @@ _SIGS = {
     "nn_batched_workspace_size": (_sz, [_i32, ctypes.c_int]),
     "nn_invert_batched": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
                                          _sz, _p]),
+    "nn_batched_autotune": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
+                                           _sz, ctypes.POINTER(ctypes.c_float)]),
+    "nn_batched_get_config": (ctypes.c_int, [_p, ctypes.c_int, _i32, ctypes.POINTER(_i32),
+                                             ctypes.POINTER(_i32)]),
+    "nn_batched_set_config": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32]),
     "nn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -279,6 +284,37 @@ def invert_batched(packed, offsets, sizes, max_n, depth=2, x0="transpose", fixed
         raise NNError(st, "nn_invert_batched")
     X._nn_ws_hold = hold  # keep the workspace alive until the caller syncs
     return X, info
+
+
+def batched_autotune(packed, offsets, sizes, max_n, depth=2, x0="transpose", fixed_iter=4,
+                     ctx: Context | None = None):
+    """nn_batched_autotune; returns (best_ms, wave_max_k, wg_per_cu)."""
+    torch = _torch()
+    batch = int(sizes.numel())
+    dt = dtype_code(packed)
+    prm = make_params(depth, x0, 0.0, 1, fixed_iter)
+    X = torch.empty_like(packed)
+    ctx = ctx or default_context(packed.device.index or 0)
+    hold, ws_ptr, ws_bytes = workspace(nn_batched_workspace_size(batch, dt), packed.device)
+    best = ctypes.c_float(0.0)
+    st = nn_batched_autotune(ctx.ptr, ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                             ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(sizes.data_ptr()),
+                             batch, int(max_n), dt, ctypes.byref(prm), ctypes.c_void_p(ws_ptr),
+                             ws_bytes, ctypes.byref(best))
+    if st != NN_OK:
+        raise NNError(st, "nn_batched_autotune")
+    wk, wg = ctypes.c_int32(), ctypes.c_int32()
+    nn_batched_get_config(ctx.ptr, dt, int(max_n), ctypes.byref(wk), ctypes.byref(wg))
+    del hold
+    return best.value, wk.value, wg.value
+
+
+def batched_set_config(dtype_code_, max_n, wave_max_k, wg_per_cu, ctx: Context | None = None,
+                       device: int = 0):
+    ctx = ctx or default_context(device)
+    st = nn_batched_set_config(ctx.ptr, int(dtype_code_), int(max_n), int(wave_max_k), int(wg_per_cu))
+    if st != NN_OK:
+        raise NNError(st, "nn_batched_set_config")
 
 
 def decode_batched_info(info_bytes):
