@@ -59,6 +59,33 @@ GemmPlan plan_gemm(Elem e, int64_t M, int64_t N);
 hipError_t launch_gemm(Elem e, bool complex_b, const GemmPlan& plan, const GemmArgs& a,
                        hipStream_t stream);
 
+// BF16-input GEMM: C = alpha * A Bt^T + E + diag * I (A: M x K, Bt: N x K, BF16
+// row-major; E, C FP32).  Optional outputs: C (FP32), Cbf (BF16 row-major),
+// CbfT (BF16 transposed), per-tile FP64 sums of squares.
+struct Bf16GemmArgs {
+  const uint16_t* A;
+  int64_t lda;
+  const uint16_t* Bt;
+  int64_t ldb;
+  int64_t M, N, K;
+  double alpha, diag;
+  const float* E;
+  int64_t lde;
+  float* C;
+  int64_t ldc;
+  uint16_t* Cbf;
+  int64_t ldcb;
+  uint16_t* CbfT;
+  int64_t ldct;
+  double* partials;
+};
+GemmPlan plan_gemm_bf16(int64_t M, int64_t N);
+hipError_t launch_gemm_bf16(const GemmPlan& plan, const Bf16GemmArgs& a, hipStream_t s);
+// FP32/FP64 -> BF16, optionally also the transposed copy (dst or dstT may be null).
+hipError_t launch_cast_bf16(bool f64, const void* src, int64_t lds, uint16_t* dst, int64_t ldd,
+                            uint16_t* dstT, int64_t ldt, int64_t rows, int64_t cols,
+                            hipStream_t s);
+
 // X_0 prologue.  scal[0] <- den (||A||_1 ||A||_inf or Re Tr A).
 hipError_t launch_den_transpose(nn_dtype dt, const void* A, int64_t lda, int64_t n, double* part,
                                 double* scal, hipStream_t s);

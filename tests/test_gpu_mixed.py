@@ -1,0 +1,77 @@
+"""Mixed-precision schedule (BF16 -> FP32 -> FP64) against the FP64 oracle.
+
+The schedule's trajectory is not pinned nest by nest (its BF16 and FP32
+phases carry their own rounding); what is pinned:
+* the final iterate: relative Frobenius difference to the oracle's converged
+  FP64 iterate (identity start, same tolerance) <= 1e-10, and its FP64 rms
+  < tol;
+* the BF16 phase products: its first nests' rms follows the oracle's FP64
+  trajectory within the BF16 perturbation (relative 2e-2), which a wrong
+  operand layout or a missing term in the BF16 GEMM would break;
+* the phase accounting: nests in phases B + F + D = iters.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_02406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+from paper_2212_02406_amd import nn  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n,cond,d", [(512, 1e4, 2), (1000, 1e4, 2), (1001, 1e3, 2), (256, 100.0, 2),
+                                      (384, 1e4, 3), (320, 1e3, 1)])
+def test_mixed_matches_fp64_oracle(n, cond, d):
+    _say(f"mixed n={n} cond={cond:g} d={d}")
+    A = W.dense_spd(n, 1.0, cond, 40 + n, log_spectrum=True)
+    Xo, io = oracle.nn_ref(A, d=d, x0=oracle.X0_SCALED_IDENTITY, tol=1e-12, max_iter=200)
+    assert io["status"] == oracle.OK
+    X, info = nn.invert(torch.from_numpy(A).to(DEV), depth=d, x0="identity", tol=1e-12,
+                        max_iter=200, prec="mixed")
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    assert info["status"] == nn.NN_OK, info
+    assert info["rms"] < 1e-12
+    rel = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    assert rel < 1e-10, rel
+    pb, pf, pd = info["phase_iters"]
+    assert pb + pf + pd == info["iters"]
+    assert pd >= 1
+    if n % 8 == 0:
+        assert pb >= 2, info["phase_iters"]
+        for k in range(min(pb, 6)):
+            a, b = info["trace"][k], io["trace"][k]
+            assert abs(a - b) <= 2e-2 * b, (k, a, b)
+    else:
+        assert pb == 0
+
+
+def test_mixed_unsupported_combinations():
+    _say("mixed unsupported")
+    A = torch.from_numpy(W.dense_spd(64, 1.0, 10.0, 3)).to(DEV)
+    for kw in (dict(x0="transpose"), dict(x0="identity", fixed_iter=3)):
+        _, info = nn.invert(A, prec="mixed", check=False, **kw)
+        assert info["status"] == nn.NN_ERR_UNSUPPORTED
+    with pytest.raises(nn.NNError):  # no workspace size exists for a non-FP64 mixed call
+        nn.invert(A.to(torch.float32), prec="mixed", x0="identity", check=False)
+
+
+def test_mixed_status_nonpositive_trace():
+    _say("mixed nonpositive trace")
+    A = torch.from_numpy(-W.dense_spd(64, 1.0, 10.0, 3)).to(DEV)
+    _, info = nn.invert(A, prec="mixed", x0="identity", check=False)
+    assert info["status"] == nn.NN_ERR_DIVERGED
