@@ -19,11 +19,14 @@
  *    >= the number of columns.  Complex values are interleaved (re, im), the
  *    layout of std::complex and of torch complex tensors.
  *  - Pointers named A, B, X, Xsol, ws, A_packed, X_packed, offsets, sizes,
- *    per_matrix are DEVICE pointers; `info` and `params` are HOST pointers.
+ *    per_matrix, pool are DEVICE pointers (nn_server_submit's A and
+ *    nn_server_fetch's dst may be host or device memory); `info`, `params`
+ *    and `stats` are HOST pointers.
  *  - The caller owns every buffer.  The library allocates no device memory
- *    in any entry point below except nn_create (a few pinned host bytes for
- *    the per-nest residual read-back).  All work for one call is enqueued on
- *    the context's stream (set by nn_create / nn_set_stream).
+ *    in any entry point below; nn_create and nn_server_create allocate a few
+ *    pinned host bytes for read-backs.  All work of nn_invert, nn_solve and
+ *    nn_invert_batched is enqueued on the context's stream (set by nn_create
+ *    / nn_set_stream); the server uses streams of its own.
  *  - A is never written.  X must not alias A or the workspace.
  *  - Argument errors return NN_ERR_ARG before any launch, and X is left
  *    untouched.  Positive statuses are warnings with a valid X (the last or
@@ -198,6 +201,119 @@ nn_status nn_batched_get_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
                                 int32_t* wave_max_k, int32_t* wg_per_cu);
 nn_status nn_batched_set_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
                                 int32_t wave_max_k, int32_t wg_per_cu);
+
+/* ---------------------------------------------------------------------------
+ * Continuous-batching server.
+ *
+ * Requests (one matrix each, with its own tolerance) are queued by
+ * nn_server_submit and advanced by nn_server_tick.  Each tick:
+ *   1. admits queued requests, first come first served (a request may be
+ *      passed by later ones that fit while it does not, at most 8 ticks in a
+ *      row), while the active count is below max_active and the request's
+ *      footprint (nn_server_footprint) fits in the free part of the caller's
+ *      device pool; admission copies A into the pool and forms X_0;
+ *   2. waits for the residual rms of every active request's current iterate
+ *      (one host synchronisation for all of them);
+ *   3. applies each request's stopping rules (those of nn_invert's tolerance
+ *      mode, per request) and either retires it or enqueues its next nest
+ *      (Sec. II-D Theorem: X <- X sum_{n=0..d} (I - A X)^n) and the residual
+ *      of the new iterate.
+ * Requests enqueue on a pool of n_streams streams (default priority), so the
+ * GEMMs of small requests run side by side on the device.  Iterates stay in
+ * the pool between ticks.  A request's result depends only on that request:
+ * every kernel's tile plan depends on (n, dtype) alone and every reduction
+ * runs in a fixed order, so a request gives the same bits alone and in any
+ * mix of co-runners.
+ *
+ * Precision: FP32 and complex64 requests iterate in their own dtype.  One
+ * whose tolerance is below wide_tol, or that stagnates above its tolerance in
+ * single precision, is promoted: A and the iterate are widened to FP64 /
+ * complex128 and the request finishes there; its result is then in the wide
+ * dtype (nn_request_info.out_dtype).  A request with tol < wide_tol reserves
+ * the wide buffers at admission; one with tol >= wide_tol reserves them only
+ * if it stagnates, and finishes STAGNATED in single precision when they do not
+ * fit.  FP64 and complex128 requests iterate in their own dtype throughout.
+ *
+ * The server is driven by one host thread (calls are not thread safe).  It
+ * allocates no device memory: everything lives in the caller's pool.  It
+ * allocates host memory and pinned host memory for the per-tick read-back
+ * (16 bytes per active slot) and creates its streams and events.
+ * ------------------------------------------------------------------------- */
+
+typedef struct nn_server nn_server;
+
+typedef struct {
+  int32_t depth;      /* inception depth d, 1 <= d <= NN_MAX_DEPTH */
+  int32_t x0;         /* NN_X0_SCALED_IDENTITY (HPD requests) or NN_X0_TRANSPOSE */
+  int32_t max_active; /* requests on the device at once, 1..65536 */
+  int32_t n_streams;  /* streams the requests are spread over, 1..8 */
+  double wide_tol;    /* tolerances below this finish in FP64 / complex128 */
+} nn_server_params;
+
+typedef struct {
+  int64_t id;         /* the caller's id */
+  int32_t status;     /* nn_status, with nn_invert's meanings */
+  int32_t iters;      /* nests applied to X_0 to obtain the result */
+  int32_t wide_iters; /* of which in FP64 / complex128 */
+  int32_t out_dtype;  /* nn_dtype of the result */
+  int64_t n;
+  double rms;         /* rms of the result, computed in the dtype it was
+                         iterated in */
+  double t_submit;    /* host seconds since server creation */
+  double t_admit;
+  double t_finish;    /* the tick that saw the stopping rule fire */
+} nn_request_info;
+
+typedef struct {
+  int32_t finished; /* requests retired by this tick */
+  int32_t active;   /* requests on the device after this tick */
+  int32_t queued;   /* requests waiting for admission */
+  int32_t ready;    /* retired requests not fetched or released yet */
+  size_t pool_used; /* pool bytes held by active and unfetched requests */
+} nn_server_stats;
+
+/* Create a server on ctx's device.  `pool` is a device buffer of pool_bytes
+ * (256-byte aligned) owned by the caller and used by the server until
+ * nn_server_destroy; params NULL selects {2, NN_X0_SCALED_IDENTITY, 1024, 4,
+ * 1e-6}. */
+nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
+                           const nn_server_params* params, nn_server** server);
+
+/* Wait for the server's device work and release it (NULL is ignored).
+ * Results not fetched are dropped. */
+void nn_server_destroy(nn_server* server);
+
+/* Pool bytes a request reserves at admission (0 for bad arguments). */
+size_t nn_server_footprint(const nn_server* server, int64_t n, nn_dtype dtype, double tol);
+
+/* Queue a request.  A (n x n, leading dimension lda, host or device memory)
+ * must stay valid and unchanged until the request is reported by
+ * nn_server_poll.  id must not be in use by a request not yet fetched or
+ * released.  Returns NN_ERR_WORKSPACE if the footprint exceeds the whole
+ * pool, NN_ERR_ARG for bad arguments; nothing is queued then. */
+nn_status nn_server_submit(nn_server* server, int64_t id, const void* A, int64_t lda, int64_t n,
+                           nn_dtype dtype, double tol, int32_t max_iter);
+
+/* One tick (see above).  Work enqueued on the context stream before the call
+ * (for instance the kernels that produce a request's A) is ordered before the
+ * tick's work.  Blocks until this tick's residuals are known.
+ * stats (optional host pointer) is filled on return.  With nothing active or
+ * admissible it returns at once. */
+nn_status nn_server_tick(nn_server* server, nn_server_stats* stats);
+
+/* Copy up to max records of retired requests not yet polled, in retirement
+ * order, into out (host); returns the count. */
+int32_t nn_server_poll(nn_server* server, nn_request_info* out, int32_t max);
+
+/* Copy a retired request's result (n x n of its out_dtype, leading dimension
+ * ldd) to dst (host or device memory) and release its pool memory.  Blocks
+ * until the copy is done.  NN_ERR_ARG if id is not a retired request; for a
+ * request that ended with an error status the copy is skipped and the
+ * memory released. */
+nn_status nn_server_fetch(nn_server* server, int64_t id, void* dst, int64_t ldd);
+
+/* Release a retired request's pool memory without copying its result. */
+nn_status nn_server_release(nn_server* server, int64_t id);
 
 /* Static description of a status code. */
 const char* nn_status_string(nn_status status);

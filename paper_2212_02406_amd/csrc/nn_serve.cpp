@@ -1,0 +1,666 @@
+// nn_serve.cpp — continuous-batching inversion server (declared in nn.h).
+//
+// Every active request advances by one NN nest per tick (Sec. II-D Theorem),
+// so a request that arrives while others are on the device starts at the next
+// tick instead of waiting for the running ones to finish.  Per tick the host
+// synchronises once: the residual rms of every active request's iterate is
+// written to its slot of a device array at the head of the pool, the array is
+// read back in one copy, each request's rules are applied on the host, and the
+// next nest and residual of every continuing request are enqueued at once.
+//
+// Per request the rules are nn_invert's tolerance-mode rules, applied per
+// precision phase, plus the promotion rules of the narrow (FP32 / complex64)
+// phase:
+//   rms not finite                              -> NONFINITE
+//   rms < tol                                   -> OK, current iterate
+//   phase nests > 0, rms >= 1, rms > previous   -> DIVERGED
+//   narrow, wide phase reserved, previous rms below the promotion point
+//     pow(1e-9, 1/(d+1)) or stagnated           -> promote (better iterate)
+//   stagnated (sqrt(N) prev < 0.1, rms >= prev) -> narrow: promote if the wide
+//                                                  buffers fit, else STAGNATED;
+//                                                  wide: STAGNATED, previous X
+//   nests == max_iter                           -> NOT_CONVERGED
+// The promotion point is one narrow nest past the rms at which the next nest
+// of order d+1 would reach about 1e-9: the narrow iterate then sits at its
+// rounding floor, and one or two wide nests finish it.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <functional>
+#include <map>
+#include <new>
+#include <queue>
+#include <unordered_map>
+#include <vector>
+
+#include "nn_internal.h"
+
+namespace nn {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxStreams = 8;
+constexpr int kMaxActiveLimit = 65536;
+constexpr int kMaxBypassTicks = 8;
+constexpr int kBypassScan = 64;
+
+inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing free list.
+class PoolAlloc {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, start = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[start] = rest;
+      used_ += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+// Matrices of one precision phase of a request.
+struct PhaseBufs {
+  nn_dtype dt = NN_F32;
+  void* A = nullptr;
+  void* X[2] = {nullptr, nullptr};
+  void* R = nullptr;
+  void* U[2] = {nullptr, nullptr};
+};
+
+struct Block {
+  size_t off = 0, bytes = 0;
+  bool held = false;
+};
+
+enum class State { Queued, Active, Retired };
+
+struct Request {
+  int64_t id = 0;
+  int64_t n = 0;
+  nn_dtype dt = NN_F32;
+  double tol = 0.0;
+  int32_t max_iter = 0;
+  const void* src = nullptr;
+  int64_t src_ld = 0;
+  State state = State::Queued;
+  int bypassed = 0;  // ticks in which later requests were admitted before it
+  Block narrow, wide;
+  bool reserve_wide = false;  // wide block reserved at admission
+  PhaseBufs ph[2];            // [0] narrow (single precision), [1] wide
+  int cur_ph = 0;
+  double* part = nullptr;     // residual GEMM tile partials
+  double* denpart = nullptr;  // norm partials of the transpose start
+  double* scal = nullptr;     // [0] den
+  int slot = -1;
+  int stream = 0;
+  bool fresh = false;  // admitted this tick: den not checked yet
+  bool polled = false;   // its record has been handed out by nn_server_poll
+  bool dropped = false;  // fetched or released before it was polled
+  int cur = 0;         // X[cur] is the current iterate
+  int iters = 0, wide_iters = 0, phase_k = 0;
+  double rms_prev = NAN;
+  int32_t status = NN_OK;
+  int result_buf = 0;  // X buffer holding the result
+  double rms = NAN;
+  double t_submit = 0, t_admit = 0, t_finish = 0;
+};
+
+bool single_dtype(nn_dtype d) { return d == NN_F32 || d == NN_C64; }
+nn_dtype widen(nn_dtype d) { return d == NN_F32 ? NN_F64 : d == NN_C64 ? NN_C128 : d; }
+Elem elem_of(nn_dtype d) { return is_double(d) ? Elem::F64 : Elem::F32; }
+
+size_t mats_per_phase(int depth) { return 4 + (depth >= 2) + (depth >= 3); }
+
+// Bytes of the per-request control region: tile partials (enough for either
+// precision's plan), norm partials, scalars.
+size_t control_bytes(int64_t n, nn_dtype dt) {
+  const int cm = is_complex(dt) ? 2 : 1;
+  const int t64 = plan_gemm(Elem::F64, n, cm * n).num_tiles();
+  const int t32 = plan_gemm(Elem::F32, n, cm * n).num_tiles();
+  return up(sizeof(double) * (size_t)std::max({t64, t32, 1})) +
+         up(sizeof(double) * den_partials_elems(n)) + up(sizeof(double) * 8);
+}
+
+size_t phase_bytes(int64_t n, nn_dtype dt, int depth) {
+  return mats_per_phase(depth) * up((size_t)n * (size_t)n * elem_size(dt));
+}
+
+}  // namespace
+}  // namespace nn
+
+using namespace nn;
+
+struct nn_server {
+  nn_ctx* ctx = nullptr;
+  char* pool = nullptr;  // start of the allocatable region
+  nn_server_params prm{};
+  int n_streams = 1;
+  PoolAlloc alloc;
+  size_t pool_bytes = 0;  // allocatable bytes
+  double* slots_dev = nullptr;   // 2 doubles per slot: rms, den
+  double* slots_host = nullptr;  // pinned
+  std::priority_queue<int, std::vector<int>, std::greater<int>> free_slots;
+  std::deque<Request*> queued;
+  std::vector<Request*> active;
+  std::unordered_map<int64_t, Request*> by_id;  // queued, active or retired (not fetched)
+  std::deque<Request*> unpolled;
+  size_t ready = 0;
+  hipStream_t streams[kMaxStreams] = {};
+  hipEvent_t done[kMaxStreams] = {};
+  hipStream_t ctl = nullptr;
+  hipEvent_t entry = nullptr;  // orders the server's streams after the context stream
+  int rr = 0;
+  std::chrono::steady_clock::time_point t0;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace nn {
+namespace {
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return NN_ERR_HIP; \
+  } while (0)
+
+size_t footprint_of(const nn_server* s, int64_t n, nn_dtype dt, double tol, bool* reserve_wide) {
+  const int d = s->prm.depth;
+  size_t b = control_bytes(n, dt) + phase_bytes(n, dt, d);
+  const bool rw = single_dtype(dt) && tol < s->prm.wide_tol;
+  if (rw) b += phase_bytes(n, widen(dt), d);
+  if (reserve_wide) *reserve_wide = rw;
+  return up(b);
+}
+
+void carve_phase(char* p, int64_t n, nn_dtype dt, int depth, PhaseBufs* out) {
+  const size_t m = up((size_t)n * (size_t)n * elem_size(dt));
+  out->dt = dt;
+  out->A = p;
+  out->X[0] = p + m;
+  out->X[1] = p + 2 * m;
+  out->R = p + 3 * m;
+  out->U[0] = depth >= 2 ? p + 4 * m : nullptr;
+  out->U[1] = depth >= 3 ? p + 5 * m : nullptr;
+}
+
+// Lay out an admitted request's first block: control region, then the start
+// phase (narrow for single-precision dtypes, else wide), then the reserved
+// wide phase if any.
+void carve_request(nn_server* s, Request* q) {
+  char* b = s->pool + q->narrow.off;
+  const int cm = is_complex(q->dt) ? 2 : 1;
+  const int t64 = plan_gemm(Elem::F64, q->n, cm * q->n).num_tiles();
+  const int t32 = plan_gemm(Elem::F32, q->n, cm * q->n).num_tiles();
+  q->part = reinterpret_cast<double*>(b);
+  b += up(sizeof(double) * (size_t)std::max({t64, t32, 1}));
+  q->denpart = reinterpret_cast<double*>(b);
+  b += up(sizeof(double) * den_partials_elems(q->n));
+  q->scal = reinterpret_cast<double*>(b);
+  b += up(sizeof(double) * 8);
+  const int d = s->prm.depth;
+  if (single_dtype(q->dt)) {
+    carve_phase(b, q->n, q->dt, d, &q->ph[0]);
+    b += phase_bytes(q->n, q->dt, d);
+    if (q->reserve_wide) carve_phase(b, q->n, widen(q->dt), d, &q->ph[1]);
+    q->cur_ph = 0;
+  } else {
+    carve_phase(b, q->n, q->dt, d, &q->ph[1]);
+    q->cur_ph = 1;
+  }
+}
+
+// Residual of the current iterate, rms into the request's slot.
+hipError_t enqueue_residual(nn_server* s, Request* q) {
+  hipStream_t st = s->streams[q->stream];
+  const PhaseBufs& P = q->ph[q->cur_ph];
+  const bool cplx = is_complex(P.dt);
+  const int64_t n = q->n, nr = (cplx ? 2 : 1) * n;
+  const GemmPlan plan = plan_gemm(elem_of(P.dt), n, nr);
+  GemmArgs g{P.A, nr, P.X[q->cur], nr, P.R, nr, nullptr, 0, n, nr, nr, -1.0, 1.0, q->part};
+  hipError_t err = launch_gemm(elem_of(P.dt), cplx, plan, g, st);
+  if (err != hipSuccess) return err;
+  return launch_rms_reduce(q->part, plan.num_tiles(), n, s->slots_dev + 2 * q->slot, st);
+}
+
+// Horner chain U_1 = R, U_{m+1} = R + R U_m, then X[cur^1] = X + X U_d.
+hipError_t enqueue_nest(nn_server* s, Request* q) {
+  hipStream_t st = s->streams[q->stream];
+  const PhaseBufs& P = q->ph[q->cur_ph];
+  const bool cplx = is_complex(P.dt);
+  const int64_t n = q->n, nr = (cplx ? 2 : 1) * n;
+  const Elem e = elem_of(P.dt);
+  const GemmPlan plan = plan_gemm(e, n, nr);
+  const void* U = P.R;
+  for (int m = 1; m < s->prm.depth; ++m) {
+    void* Un = P.U[(m - 1) & 1];
+    GemmArgs g{P.R, nr, U, nr, Un, nr, P.R, nr, n, nr, nr, 1.0, 0.0, nullptr};
+    hipError_t err = launch_gemm(e, cplx, plan, g, st);
+    if (err != hipSuccess) return err;
+    U = Un;
+  }
+  GemmArgs g{P.X[q->cur], nr, U, nr, P.X[q->cur ^ 1], nr, P.X[q->cur], nr, n, nr, nr, 1.0, 0.0,
+             nullptr};
+  return launch_gemm(e, cplx, plan, g, st);
+}
+
+// Copy A into the pool, form den and X_0, copy den to the slot, residual.
+hipError_t enqueue_start(nn_server* s, Request* q) {
+  hipStream_t st = s->streams[q->stream];
+  const PhaseBufs& P = q->ph[q->cur_ph];
+  const size_t e = elem_size(q->dt);
+  hipError_t err = hipMemcpy2DAsync(P.A, (size_t)q->n * e, q->src, (size_t)q->src_ld * e,
+                                    (size_t)q->n * e, (size_t)q->n, hipMemcpyDefault, st);
+  if (err != hipSuccess) return err;
+  if (s->prm.x0 == NN_X0_TRANSPOSE) {
+    err = launch_den_transpose(q->dt, P.A, q->n, q->n, q->denpart, q->scal, st);
+    if (err == hipSuccess) err = launch_x0_transpose(q->dt, P.A, q->n, P.X[0], q->n, q->n, q->scal, st);
+  } else {
+    err = launch_den_trace(q->dt, P.A, q->n, q->n, q->scal, st);
+    if (err == hipSuccess) err = launch_x0_identity(q->dt, P.X[0], q->n, q->n, q->scal, st);
+  }
+  if (err != hipSuccess) return err;
+  err = hipMemcpyAsync(s->slots_dev + 2 * q->slot + 1, q->scal, sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  if (err != hipSuccess) return err;
+  q->cur = 0;
+  return enqueue_residual(s, q);
+}
+
+// Widen A and the iterate X[from] into the wide phase, then its residual.
+hipError_t enqueue_promote(nn_server* s, Request* q, int from) {
+  hipStream_t st = s->streams[q->stream];
+  const PhaseBufs& N = q->ph[0];
+  const PhaseBufs& W = q->ph[1];
+  const int64_t n = q->n, nr = (is_complex(q->dt) ? 2 : 1) * n;
+  hipError_t err = launch_cast_f32_f64(static_cast<const float*>(N.A), nr,
+                                       static_cast<double*>(W.A), nr, n, nr, st);
+  if (err != hipSuccess) return err;
+  err = launch_cast_f32_f64(static_cast<const float*>(N.X[from]), nr,
+                            static_cast<double*>(W.X[0]), nr, n, nr, st);
+  if (err != hipSuccess) return err;
+  q->cur_ph = 1;
+  q->cur = 0;
+  q->phase_k = 0;
+  q->rms_prev = NAN;
+  return enqueue_residual(s, q);
+}
+
+void release_blocks(nn_server* s, Request* q) {
+  if (q->narrow.held) s->alloc.release(q->narrow.off, q->narrow.bytes);
+  if (q->wide.held) s->alloc.release(q->wide.off, q->wide.bytes);
+  q->narrow.held = q->wide.held = false;
+}
+
+void retire(nn_server* s, Request* q, int32_t status, double rms, int result_buf) {
+  q->status = status;
+  q->rms = rms;
+  q->result_buf = result_buf;
+  q->state = State::Retired;
+  q->t_finish = s->now();
+  s->free_slots.push(q->slot);
+  q->slot = -1;
+  s->unpolled.push_back(q);
+  ++s->ready;
+}
+
+// Try to reserve the wide block of a request that did not reserve it.
+bool reserve_wide_late(nn_server* s, Request* q) {
+  if (q->ph[1].A) return true;
+  const size_t b = up(phase_bytes(q->n, widen(q->dt), s->prm.depth));
+  size_t off;
+  if (!s->alloc.alloc(b, &off)) return false;
+  q->wide = {off, b, true};
+  carve_phase(s->pool + off, q->n, widen(q->dt), s->prm.depth, &q->ph[1]);
+  return true;
+}
+
+nn_status admit(nn_server* s) {
+  int scanned = 0;
+  bool head_blocked = false;
+  for (auto it = s->queued.begin(); it != s->queued.end() && scanned < kBypassScan;) {
+    if ((int)s->active.size() >= s->prm.max_active) break;
+    Request* q = *it;
+    ++scanned;
+    size_t off;
+    const size_t b = footprint_of(s, q->n, q->dt, q->tol, &q->reserve_wide);
+    if (!s->alloc.alloc(b, &off)) {
+      if (!head_blocked) {
+        head_blocked = true;
+        // A request passed over too often holds the line: admit nothing after it.
+        if (q->bypassed >= kMaxBypassTicks) break;
+        ++q->bypassed;
+      }
+      ++it;
+      continue;
+    }
+    q->narrow = {off, b, true};
+    carve_request(s, q);
+    q->slot = s->free_slots.top();
+    s->free_slots.pop();
+    q->stream = s->rr++ % s->n_streams;
+    q->state = State::Active;
+    q->fresh = true;
+    q->t_admit = s->now();
+    HIP_TRY(enqueue_start(s, q));
+    s->active.push_back(q);
+    it = s->queued.erase(it);
+  }
+  return NN_OK;
+}
+
+// Apply the rules to one active request whose rms (and den, if fresh) are in
+// the read-back.  Returns false if it retired.
+nn_status step_request(nn_server* s, Request* q, bool* keep) {
+  const double* h = s->slots_host + 2 * q->slot;
+  *keep = false;
+  if (q->fresh) {
+    q->fresh = false;
+    const double den = h[1];
+    if (!isfinite(den) || den <= 0.0) {
+      retire(s, q, isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE, NAN, q->cur);
+      return NN_OK;
+    }
+  }
+  const double rms = h[0];
+  const bool narrow = q->cur_ph == 0;
+  const double sqn = sqrt((double)q->n);
+  if (!isfinite(rms)) {
+    retire(s, q, NN_ERR_NONFINITE, rms, q->cur);
+    return NN_OK;
+  }
+  if (rms < q->tol) {
+    retire(s, q, NN_OK, rms, q->cur);
+    return NN_OK;
+  }
+  if (q->phase_k > 0 && rms >= 1.0 && rms > q->rms_prev) {
+    retire(s, q, NN_ERR_DIVERGED, rms, q->cur);
+    return NN_OK;
+  }
+  const bool stagnated = q->phase_k > 0 && sqn * q->rms_prev < 0.1 && rms >= q->rms_prev;
+  if (narrow) {
+    const double point = pow(1e-9, 1.0 / (s->prm.depth + 1));
+    const bool early = q->reserve_wide && q->phase_k > 0 && q->rms_prev < point;
+    if (early || stagnated) {
+      if (reserve_wide_late(s, q)) {
+        const bool back = q->phase_k > 0 && q->rms_prev <= rms;  // continue from X_{k-1}
+        if (back) --q->iters;
+        HIP_TRY(enqueue_promote(s, q, back ? q->cur ^ 1 : q->cur));
+        *keep = true;
+        return NN_OK;
+      }
+      if (stagnated) {
+        --q->iters;
+        retire(s, q, NN_STAGNATED, q->rms_prev, q->cur ^ 1);
+        return NN_OK;
+      }
+    }
+  } else if (stagnated) {
+    --q->iters;
+    --q->wide_iters;
+    retire(s, q, NN_STAGNATED, q->rms_prev, q->cur ^ 1);
+    return NN_OK;
+  }
+  if (q->iters >= q->max_iter) {
+    retire(s, q, NN_NOT_CONVERGED, rms, q->cur);
+    return NN_OK;
+  }
+  q->rms_prev = rms;
+  HIP_TRY(enqueue_nest(s, q));
+  q->cur ^= 1;
+  ++q->iters;
+  ++q->phase_k;
+  if (!narrow) ++q->wide_iters;
+  HIP_TRY(enqueue_residual(s, q));
+  *keep = true;
+  return NN_OK;
+}
+
+void fill_stats(const nn_server* s, int fin, nn_server_stats* st) {
+  if (!st) return;
+  st->finished = fin;
+  st->active = (int32_t)s->active.size();
+  st->queued = (int32_t)s->queued.size();
+  st->ready = (int32_t)s->ready;
+  st->pool_used = s->alloc.used();
+}
+
+Request* find_retired(nn_server* s, int64_t id) {
+  auto it = s->by_id.find(id);
+  if (it == s->by_id.end() || it->second->state != State::Retired) return nullptr;
+  return it->second;
+}
+
+// Release a retired request; its record is freed now if it was polled, else
+// by the poll that skips it.
+void drop(nn_server* s, Request* q) {
+  release_blocks(s, q);
+  s->by_id.erase(q->id);
+  --s->ready;
+  if (q->polled)
+    delete q;
+  else
+    q->dropped = true;
+}
+
+}  // namespace
+}  // namespace nn
+
+extern "C" {
+
+nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
+                           const nn_server_params* params, nn_server** out) {
+  if (!ctx || !pool || !out) return NN_ERR_ARG;
+  nn_server_params p{2, NN_X0_SCALED_IDENTITY, 1024, 4, 1e-6};
+  if (params) p = *params;
+  if (p.depth < 1 || p.depth > NN_MAX_DEPTH) return NN_ERR_ARG;
+  if (p.x0 != NN_X0_SCALED_IDENTITY && p.x0 != NN_X0_TRANSPOSE) return NN_ERR_ARG;
+  if (p.max_active < 1 || p.max_active > kMaxActiveLimit) return NN_ERR_ARG;
+  if (p.n_streams < 1 || p.n_streams > kMaxStreams) return NN_ERR_ARG;
+  if (!(p.wide_tol >= 0.0)) return NN_ERR_ARG;
+  const size_t head = up(2 * sizeof(double) * (size_t)p.max_active);
+  if ((reinterpret_cast<uintptr_t>(pool) & (kAlign - 1)) || pool_bytes <= head)
+    return NN_ERR_WORKSPACE;
+  nn_server* s = new (std::nothrow) nn_server();
+  if (!s) return NN_ERR_HIP;
+  s->ctx = ctx;
+  s->prm = p;
+  s->n_streams = p.n_streams;
+  s->slots_dev = static_cast<double*>(pool);
+  s->pool = static_cast<char*>(pool) + head;
+  s->pool_bytes = (pool_bytes - head) / kAlign * kAlign;
+  s->alloc.reset(s->pool_bytes);
+  for (int i = 0; i < p.max_active; ++i) s->free_slots.push(i);
+  s->t0 = std::chrono::steady_clock::now();
+  bool ok = hipSetDevice(ctx->device) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&s->slots_host),
+                          2 * sizeof(double) * (size_t)p.max_active, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&s->entry, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < s->n_streams; ++i)
+    ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    nn_server_destroy(s);
+    return NN_ERR_HIP;
+  }
+  *out = s;
+  return NN_OK;
+}
+
+void nn_server_destroy(nn_server* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->ctx->device);
+  for (int i = 0; i < kMaxStreams; ++i) {
+    if (s->streams[i]) {
+      (void)hipStreamSynchronize(s->streams[i]);
+      (void)hipStreamDestroy(s->streams[i]);
+    }
+    if (s->done[i]) (void)hipEventDestroy(s->done[i]);
+  }
+  if (s->ctl) {
+    (void)hipStreamSynchronize(s->ctl);
+    (void)hipStreamDestroy(s->ctl);
+  }
+  if (s->entry) (void)hipEventDestroy(s->entry);
+  if (s->slots_host) (void)hipHostFree(s->slots_host);
+  std::vector<Request*> all;
+  for (auto& kv : s->by_id) all.push_back(kv.second);
+  for (Request* q : s->unpolled)
+    if (q->dropped) all.push_back(q);  // released before it was polled
+  for (Request* q : all) delete q;
+  delete s;
+}
+
+size_t nn_server_footprint(const nn_server* s, int64_t n, nn_dtype dtype, double tol) {
+  if (!s || n < 1 || dtype < NN_F64 || dtype > NN_C128 || !(tol >= 0.0)) return 0;
+  return footprint_of(s, n, dtype, tol, nullptr);
+}
+
+nn_status nn_server_submit(nn_server* s, int64_t id, const void* A, int64_t lda, int64_t n,
+                           nn_dtype dtype, double tol, int32_t max_iter) {
+  if (!s || !A || n < 1 || lda < n || !(tol >= 0.0) || max_iter < 1) return NN_ERR_ARG;
+  if (dtype < NN_F64 || dtype > NN_C128) return NN_ERR_ARG;
+  if (s->by_id.count(id)) return NN_ERR_ARG;
+  if (footprint_of(s, n, dtype, tol, nullptr) > s->pool_bytes) return NN_ERR_WORKSPACE;
+  Request* q = new (std::nothrow) Request();
+  if (!q) return NN_ERR_HIP;
+  q->id = id;
+  q->n = n;
+  q->dt = dtype;
+  q->tol = tol;
+  q->max_iter = max_iter;
+  q->src = A;
+  q->src_ld = lda;
+  q->t_submit = s->now();
+  s->queued.push_back(q);
+  s->by_id[id] = q;
+  return NN_OK;
+}
+
+nn_status nn_server_tick(nn_server* s, nn_server_stats* stats) {
+  if (!s) return NN_ERR_ARG;
+  if (hipSetDevice(s->ctx->device) != hipSuccess) return NN_ERR_HIP;
+  // Work the caller enqueued on the context stream (e.g. producing A) comes first.
+  HIP_TRY(hipEventRecord(s->entry, s->ctx->stream));
+  for (int i = 0; i < s->n_streams; ++i) HIP_TRY(hipStreamWaitEvent(s->streams[i], s->entry, 0));
+  nn_status st = admit(s);
+  if (st != NN_OK) return st;
+  if (s->active.empty()) {
+    fill_stats(s, 0, stats);
+    return NN_OK;
+  }
+  int hi = 0;
+  for (Request* q : s->active) hi = std::max(hi, q->slot + 1);
+  for (int i = 0; i < s->n_streams; ++i) {
+    HIP_TRY(hipEventRecord(s->done[i], s->streams[i]));
+    HIP_TRY(hipStreamWaitEvent(s->ctl, s->done[i], 0));
+  }
+  HIP_TRY(hipMemcpyAsync(s->slots_host, s->slots_dev, 2 * sizeof(double) * (size_t)hi,
+                         hipMemcpyDeviceToHost, s->ctl));
+  HIP_TRY(hipStreamSynchronize(s->ctl));
+  int fin = 0;
+  std::vector<Request*> still;
+  still.reserve(s->active.size());
+  for (Request* q : s->active) {
+    bool keep = false;
+    st = step_request(s, q, &keep);
+    if (st != NN_OK) return st;
+    if (keep)
+      still.push_back(q);
+    else
+      ++fin;
+  }
+  s->active.swap(still);
+  fill_stats(s, fin, stats);
+  return NN_OK;
+}
+
+int32_t nn_server_poll(nn_server* s, nn_request_info* out, int32_t max) {
+  if (!s || !out || max < 1) return 0;
+  int32_t k = 0;
+  while (k < max && !s->unpolled.empty()) {
+    Request* q = s->unpolled.front();
+    s->unpolled.pop_front();
+    if (q->dropped) {
+      delete q;
+      continue;
+    }
+    q->polled = true;
+    nn_request_info& r = out[k++];
+    r.id = q->id;
+    r.status = q->status;
+    r.iters = q->iters;
+    r.wide_iters = q->wide_iters;
+    r.out_dtype = q->ph[q->cur_ph].dt;
+    r.n = q->n;
+    r.rms = q->rms;
+    r.t_submit = q->t_submit;
+    r.t_admit = q->t_admit;
+    r.t_finish = q->t_finish;
+  }
+  return k;
+}
+
+nn_status nn_server_fetch(nn_server* s, int64_t id, void* dst, int64_t ldd) {
+  if (!s || !dst) return NN_ERR_ARG;
+  Request* q = find_retired(s, id);
+  if (!q || ldd < q->n) return NN_ERR_ARG;
+  if (q->status >= 0) {
+    const PhaseBufs& P = q->ph[q->cur_ph];
+    const size_t e = elem_size(P.dt);
+    hipStream_t st = s->streams[q->stream];
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)ldd * e, P.X[q->result_buf], (size_t)q->n * e,
+                             (size_t)q->n * e, (size_t)q->n, hipMemcpyDefault, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  drop(s, q);
+  return NN_OK;
+}
+
+nn_status nn_server_release(nn_server* s, int64_t id) {
+  if (!s) return NN_ERR_ARG;
+  Request* q = find_retired(s, id);
+  if (!q) return NN_ERR_ARG;
+  drop(s, q);
+  return NN_OK;
+}
+
+}  // extern "C"

@@ -62,6 +62,27 @@ class nn_info_dev(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rms", ctypes.c_double)]
 
 
+class nn_server_params(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("x0", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("wide_tol", ctypes.c_double)]
+
+
+class nn_request_info(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("wide_iters", ctypes.c_int32), ("out_dtype", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("rms", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_finish", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class nn_server_stats(ctypes.Structure):
+    _fields_ = [("finished", ctypes.c_int32), ("active", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("ready", ctypes.c_int32),
+                ("pool_used", ctypes.c_size_t)]
+
+
 _p, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
 _PP = ctypes.POINTER(nn_params)
 _SIGS = {
@@ -82,6 +103,16 @@ _SIGS = {
     "nn_batched_get_config": (ctypes.c_int, [_p, ctypes.c_int, _i32, ctypes.POINTER(_i32),
                                              ctypes.POINTER(_i32)]),
     "nn_batched_set_config": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32]),
+    "nn_server_create": (ctypes.c_int, [_p, _p, _sz, ctypes.POINTER(nn_server_params),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "nn_server_destroy": (None, [_p]),
+    "nn_server_footprint": (_sz, [_p, _i64, ctypes.c_int, ctypes.c_double]),
+    "nn_server_submit": (ctypes.c_int, [_p, _i64, _p, _i64, _i64, ctypes.c_int, ctypes.c_double,
+                                        _i32]),
+    "nn_server_tick": (ctypes.c_int, [_p, ctypes.POINTER(nn_server_stats)]),
+    "nn_server_poll": (_i32, [_p, ctypes.POINTER(nn_request_info), _i32]),
+    "nn_server_fetch": (ctypes.c_int, [_p, _i64, _p, _i64]),
+    "nn_server_release": (ctypes.c_int, [_p, _i64]),
     "nn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -324,3 +355,104 @@ def decode_batched_info(info_bytes):
     rec = np.frombuffer(raw.tobytes(), dtype=np.dtype([("iters", "<i4"), ("status", "<i4"),
                                                         ("rms", "<f8")]))
     return rec["iters"].copy(), rec["status"].copy(), rec["rms"].copy()
+
+
+# ---- continuous-batching server ----------------------------------------------
+
+_TORCH_OF = {NN_F64: "float64", NN_F32: "float32", NN_C64: "complex64", NN_C128: "complex128"}
+
+
+class Server:
+    """nn_server over a torch-owned device pool of ``pool_bytes``.
+
+    submit(id, A, tol, max_iter) queues a device (or host) matrix; tick()
+    advances every active request by one nest; poll() returns the records of
+    retired requests; fetch(id) returns the result as a new tensor (on
+    ``out_device``) and frees its pool memory.  Source tensors are kept
+    referenced until their request is polled.
+    """
+
+    def __init__(self, pool_bytes, depth=2, x0="identity", max_active=1024, n_streams=4,
+                 wide_tol=1e-6, device=0, ctx: Context | None = None):
+        torch = _torch()
+        self.ctx = ctx or default_context(device)
+        self.device = torch.device("cuda", device)
+        self._pool = workspace(int(pool_bytes), self.device)
+        p = nn_server_params()
+        p.depth, p.x0 = int(depth), X0_NAMES[x0] if isinstance(x0, str) else int(x0)
+        p.max_active, p.n_streams, p.wide_tol = int(max_active), int(n_streams), float(wide_tol)
+        self.params = p
+        self._ptr = ctypes.c_void_p()
+        st = nn_server_create(self.ctx.ptr, ctypes.c_void_p(self._pool[1]), self._pool[2],
+                              ctypes.byref(p), ctypes.byref(self._ptr))
+        if st != NN_OK:
+            raise NNError(st, "nn_server_create")
+        self._src = {}
+        self.stats = nn_server_stats()
+        self._rec = (nn_request_info * 256)()
+
+    def footprint(self, n, dtype, tol):
+        return nn_server_footprint(self._ptr, int(n), int(dtype), float(tol))
+
+    def submit(self, rid, A, tol, max_iter=100):
+        if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+            raise ValueError("A must be a square row-major matrix")
+        st = nn_server_submit(self._ptr, int(rid), ctypes.c_void_p(A.data_ptr()), A.stride(0),
+                              A.shape[0], dtype_code(A), float(tol), int(max_iter))
+        if st != NN_OK:
+            raise NNError(st, "nn_server_submit")
+        self._src[int(rid)] = A
+
+    def tick(self):
+        st = nn_server_tick(self._ptr, ctypes.byref(self.stats))
+        if st != NN_OK:
+            raise NNError(st, "nn_server_tick")
+        return self.stats
+
+    def poll(self):
+        out = []
+        while True:
+            k = nn_server_poll(self._ptr, self._rec, len(self._rec))
+            for i in range(k):
+                d = self._rec[i].as_dict()
+                self._src.pop(d["id"], None)
+                out.append(d)
+            if k < len(self._rec):
+                return out
+
+    def fetch(self, rid, n, out_dtype, out_device=None):
+        torch = _torch()
+        dev = self.device if out_device is None else torch.device(out_device)
+        X = torch.empty((int(n), int(n)), dtype=getattr(torch, _TORCH_OF[int(out_dtype)]),
+                        device=dev, pin_memory=(dev.type == "cpu"))
+        st = nn_server_fetch(self._ptr, int(rid), ctypes.c_void_p(X.data_ptr()), int(n))
+        if st != NN_OK:
+            raise NNError(st, "nn_server_fetch")
+        return X
+
+    def release(self, rid):
+        st = nn_server_release(self._ptr, int(rid))
+        if st != NN_OK:
+            raise NNError(st, "nn_server_release")
+
+    def run_until_idle(self, max_ticks=100000):
+        """Tick until nothing is queued or active; returns the polled records."""
+        recs = []
+        for _ in range(max_ticks):
+            s = self.tick()
+            recs += self.poll()
+            if s.active == 0 and s.queued == 0:
+                return recs
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        if self._ptr:
+            nn_server_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+        self._src.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

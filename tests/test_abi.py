@@ -33,6 +33,23 @@ def test_struct_layout():
     assert nn.nn_info.rms_trace.offset == 48
     assert ctypes.sizeof(nn.nn_info) == 48 + 8 * nn.NN_TRACE_MAX
     assert ctypes.sizeof(nn.nn_info_dev) == 16
+    assert ctypes.sizeof(nn.nn_server_params) == 24
+    assert ctypes.sizeof(nn.nn_request_info) == 64
+    assert nn.nn_request_info.rms.offset == 32
+    assert ctypes.sizeof(nn.nn_server_stats) == 24
+
+
+def test_server_argument_errors_before_device_work():
+    nn = _nn()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert nn.nn_server_create(None, fake, 1 << 20, None, ctypes.byref(out)) == nn.NN_ERR_ARG
+    assert nn.nn_server_footprint(None, 64, nn.NN_F32, 1e-4) == 0
+    assert nn.nn_server_submit(None, 1, fake, 4, 4, nn.NN_F32, 1e-4, 10) == nn.NN_ERR_ARG
+    assert nn.nn_server_tick(None, None) == nn.NN_ERR_ARG
+    assert nn.nn_server_fetch(None, 1, fake, 4) == nn.NN_ERR_ARG
+    assert nn.nn_server_release(None, 1) == nn.NN_ERR_ARG
+    nn.nn_server_destroy(None)
 
 
 def test_status_strings():

@@ -1,0 +1,284 @@
+"""Continuous-batching server (nn_server_*) against the oracle and against
+itself alone vs in a mix.
+
+Parity bars:
+* A request that finishes in single precision runs exactly the kernels of
+  nn_invert in that dtype (same plans, same reductions, scaled identity
+  start), so its result, iteration count and rms equal nn_invert's
+  tolerance-mode call bit for bit.
+* Against the FP64 oracle at the request's tolerance: both results satisfy
+  ||X - A^-1||_F / ||A^-1||_F <= ||I - A X||_F = sqrt(N) rms (A^-1 (A X - I)),
+  so ||X - X_oracle||_F / ||X_oracle||_F <= 1.05 sqrt(N) (rms + rms_oracle),
+  with rms the true residual of the served X computed here in FP64.
+* Served rms: a wide (FP64 / complex128) result has its rms formed in FP64,
+  so the true rms is below tol (1 + 1e-6) + 1e-13; a single-precision result
+  had its residual formed in FP32 with N <= 512 and cond <= 1e3, where the
+  FP32-formed rms is within 1e-6 absolute of the true one, so the true rms is
+  below tol + 1e-6.
+* Alone vs in a mix: bitwise identical X, iterations and status.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_02406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+from paper_2212_02406_amd import nn  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MB = 1 << 20
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _mat(n, cond, seed, cplx):
+    return W.dense_spd(n, 1.0, cond, seed, log_spectrum=True, complex_=cplx,
+                       dtype=np.complex64 if cplx else np.float32)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _serve(reqs, pool_bytes=1024 * MB, stagger=0, **kw):
+    """Run requests [(id, A_host, tol, max_iter)] through a fresh server.
+    stagger > 0 submits the requests in groups of `stagger`, one group per
+    tick.  Returns {id: (record, X host array)}."""
+    srv = nn.Server(pool_bytes, **kw)
+    dev = {rid: _dev(A) for rid, A, _, _ in reqs}
+    torch.cuda.synchronize()
+    out = {}
+    pending = list(reqs)
+    ticks = 0
+    while True:
+        take = pending if stagger <= 0 else pending[:stagger]
+        for rid, A, tol, mi in take:
+            srv.submit(rid, dev[rid], tol, mi)
+        pending = pending[len(take):]
+        s = srv.tick()
+        ticks += 1
+        for r in srv.poll():
+            X = srv.fetch(r["id"], r["n"], r["out_dtype"], out_device="cpu") if r["status"] >= 0 \
+                else None
+            if X is None:
+                srv.release(r["id"])
+            out[r["id"]] = (r, None if X is None else X.numpy().copy())
+        if not pending and s.active == 0 and s.queued == 0:
+            break
+        assert ticks < 10000
+    srv.close()
+    return out
+
+
+def _true_rms(A, X):
+    A64 = A.astype(np.complex128 if np.iscomplexobj(A) else np.float64)
+    R = np.eye(A.shape[0]) - A64 @ X.astype(A64.dtype)
+    return float(np.sqrt(np.sum(np.abs(R) ** 2) / A.shape[0]))
+
+
+def _check_vs_oracle(A, rec, X, tol):
+    n = A.shape[0]
+    A64 = A.astype(np.complex128 if np.iscomplexobj(A) else np.float64)
+    Xo, io = oracle.nn_ref(A64, d=2, x0=oracle.X0_SCALED_IDENTITY, tol=tol, max_iter=100)
+    assert io["status"] == oracle.OK
+    rt = _true_rms(A, X)
+    if rec["wide_iters"] > 0:
+        assert rt < tol * (1 + 1e-6) + 1e-13, (rec, rt)
+    else:
+        assert rt < tol + 1e-6, (rec, rt)
+    e = np.linalg.norm(X.astype(Xo.dtype) - Xo) / np.linalg.norm(Xo)
+    assert e <= 1.05 * np.sqrt(n) * (rt + io["rms"]), (rec, e, rt, io["rms"])
+    return e
+
+
+CASES = [(32, 10.0, False), (100, 100.0, True), (257, 1e3, False), (384, 50.0, True),
+         (512, 1e3, True), (129, 1e3, False)]
+
+
+def test_single_precision_results_equal_nn_invert():
+    _say("serve narrow == nn_invert")
+    reqs = [(i, _mat(n, c, 100 + i, cx), 1e-4, 100) for i, (n, c, cx) in enumerate(CASES)]
+    res = _serve(reqs)
+    for rid, A, tol, _ in reqs:
+        rec, X = res[rid]
+        assert rec["status"] == nn.NN_OK and rec["wide_iters"] == 0, rec
+        Xi, info = nn.invert(_dev(A), depth=2, x0="identity", tol=tol, max_iter=100)
+        torch.cuda.synchronize()
+        assert info["status"] == nn.NN_OK and info["iters"] == rec["iters"], (info, rec)
+        assert info["rms"] == rec["rms"]
+        assert np.array_equal(Xi.cpu().numpy(), X), rid
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8])
+def test_served_results_match_oracle(tol):
+    _say(f"serve vs oracle tol={tol}")
+    reqs = [(i, _mat(n, c, 200 + i, cx), tol, 100) for i, (n, c, cx) in enumerate(CASES)]
+    res = _serve(reqs)
+    for rid, A, _, _ in reqs:
+        rec, X = res[rid]
+        assert rec["status"] == nn.NN_OK, rec
+        if tol < 1e-6:
+            assert rec["wide_iters"] > 0
+            assert rec["out_dtype"] == (nn.NN_C128 if np.iscomplexobj(A) else nn.NN_F64)
+            assert X.dtype == (np.complex128 if np.iscomplexobj(A) else np.float64)
+        _check_vs_oracle(A, rec, X, tol)
+
+
+def test_alone_vs_mix_bitwise():
+    """Requests arriving while others run give the same bits as alone."""
+    _say("serve alone vs mix")
+    g = W.rng(7)
+    reqs = []
+    for i in range(24):
+        n = int(np.rint(np.exp(g.uniform(np.log(32), np.log(600)))))
+        cond = float(np.exp(g.uniform(np.log(10), np.log(1e3))))
+        cx = bool(g.uniform() < 0.5)
+        tol = 1e-4 if g.uniform() < 0.5 else 1e-8
+        reqs.append((i, _mat(n, cond, 300 + i, cx), tol, 100))
+    mix = _serve(reqs, stagger=3, max_active=8)
+    for req in reqs[::3] + reqs[1:6]:
+        alone = _serve([req])
+        ra, Xa = alone[req[0]]
+        rm, Xm = mix[req[0]]
+        for k in ("status", "iters", "wide_iters", "out_dtype", "rms"):
+            assert ra[k] == rm[k], (k, ra, rm)
+        assert np.array_equal(Xa, Xm), req[0]
+
+
+def test_admission_by_footprint():
+    """A pool that holds two requests at a time: never more are active, all
+    finish, FIFO order among equal requests."""
+    _say("serve admission")
+    n = 512
+    mats = [_mat(n, 100.0, 400 + i, False) for i in range(5)]
+    probe = nn.Server(64 * MB)
+    fp = probe.footprint(n, nn.NN_F32, 1e-4)
+    probe.close()
+    head = 256 * 1024
+    srv = nn.Server(head + 2 * fp + fp // 2, max_active=1024)
+    devs = [_dev(m) for m in mats]
+    torch.cuda.synchronize()
+    for i, A in enumerate(devs):
+        srv.submit(i, A, 1e-4, 100)
+    recs, peak = [], 0
+    for _ in range(1000):
+        s = srv.tick()
+        peak = max(peak, s.active)
+        assert s.pool_used <= 2 * fp + fp // 2
+        for r in srv.poll():
+            X = srv.fetch(r["id"], r["n"], r["out_dtype"], out_device="cpu").numpy()
+            recs.append(r)
+            _check_vs_oracle(mats[r["id"]], r, X, 1e-4)
+        if s.active == 0 and s.queued == 0:
+            break
+    srv.close()
+    assert peak == 2 and len(recs) == 5
+    admits = [r["t_admit"] for r in sorted(recs, key=lambda r: r["id"])]
+    assert admits == sorted(admits)
+
+
+def test_small_requests_pass_a_large_one_that_does_not_fit():
+    _say("serve bypass")
+    big = [_mat(700, 100.0, 500 + i, False) for i in range(2)]
+    small = [_mat(48, 100.0, 510 + i, True) for i in range(4)]
+    probe = nn.Server(64 * MB)
+    fpb = probe.footprint(700, nn.NN_F32, 1e-4)
+    fps = probe.footprint(48, nn.NN_C64, 1e-4)
+    probe.close()
+    srv = nn.Server(256 * 1024 + fpb + 4 * fps + 4096)
+    dv = [_dev(m) for m in big + small]
+    torch.cuda.synchronize()
+    for i, A in enumerate(dv):
+        srv.submit(i, A, 1e-4, 100)
+    s = srv.tick()
+    assert s.active == 5 and s.queued == 1  # big[1] waits, the small ones pass it
+    recs = []
+    for _ in range(1000):  # results are released as they retire, freeing the pool
+        s = srv.tick()
+        for r in srv.poll():
+            assert r["status"] == nn.NN_OK
+            srv.release(r["id"])
+            recs.append(r)
+        if s.active == 0 and s.queued == 0:
+            break
+    assert sorted(r["id"] for r in recs) == list(range(6))
+    big1 = next(r for r in recs if r["id"] == 1)
+    assert big1["t_admit"] >= max(r["t_finish"] for r in recs if r["id"] == 0)
+    srv.close()
+
+
+def test_host_source_equals_device_source():
+    _say("serve host source")
+    A = _mat(200, 100.0, 600, True)
+    srv = nn.Server(256 * MB)
+    Ah = torch.from_numpy(A).pin_memory()
+    Ad = _dev(A)
+    torch.cuda.synchronize()
+    srv.submit(1, Ah, 1e-8, 100)
+    srv.submit(2, Ad, 1e-8, 100)
+    recs = {r["id"]: r for r in srv.run_until_idle()}
+    X1 = srv.fetch(1, 200, recs[1]["out_dtype"], out_device="cpu").numpy()
+    X2 = srv.fetch(2, 200, recs[2]["out_dtype"], "cuda:0").cpu().numpy()
+    srv.close()
+    assert np.array_equal(X1, X2)
+
+
+def test_statuses_match_oracle_rules():
+    _say("serve statuses")
+    n = 64
+    neg = -np.eye(n, dtype=np.float32)
+    nan = _mat(n, 10.0, 700, False)
+    nan[3, 5] = np.nan
+    slow = _mat(n, 1e3, 701, False)
+    floor = _mat(n, 1e3, 702, True)
+    reqs = [(0, neg, 1e-4, 100), (1, nan, 1e-4, 100), (2, slow, 1e-4, 2), (3, floor, 0.0, 100)]
+    res = _serve(reqs)
+    assert res[0][0]["status"] == nn.NN_ERR_DIVERGED and res[0][0]["iters"] == 0
+    assert res[1][0]["status"] == nn.NN_ERR_NONFINITE
+    assert res[2][0]["status"] == nn.NN_NOT_CONVERGED and res[2][0]["iters"] == 2
+    r3, X3 = res[3]
+    assert r3["status"] == nn.NN_STAGNATED and r3["wide_iters"] > 0
+    assert r3["out_dtype"] == nn.NN_C128
+    # the oracle's statuses for the same inputs and rules
+    _, io = oracle.nn_ref(neg.astype(np.float64), d=2, x0=oracle.X0_SCALED_IDENTITY, tol=1e-4)
+    assert io["status"] == oracle.ERR_DIVERGED
+    _, io = oracle.nn_ref(slow.astype(np.float64), d=2, x0=oracle.X0_SCALED_IDENTITY, tol=1e-4,
+                          max_iter=2)
+    assert io["status"] == oracle.NOT_CONVERGED and io["iters"] == 2
+    assert _true_rms(floor, X3) < 1e-12
+
+
+def test_argument_errors():
+    _say("serve arg errors")
+    srv = nn.Server(16 * MB)
+    A = _dev(_mat(32, 10.0, 800, False))
+    torch.cuda.synchronize()
+    srv.submit(5, A, 1e-4)
+    with pytest.raises(nn.NNError):
+        srv.submit(5, A, 1e-4)  # id in use
+    with pytest.raises(nn.NNError):
+        srv.submit(6, A, -1.0)
+    big = torch.zeros((4096, 4096), dtype=torch.float32, device=DEV)
+    with pytest.raises(nn.NNError) as e:
+        srv.submit(7, big, 1e-4)
+    assert e.value.status == nn.NN_ERR_WORKSPACE
+    with pytest.raises(nn.NNError):
+        srv.release(5)  # not retired yet
+    recs = srv.run_until_idle()
+    assert [r["id"] for r in recs] == [5]
+    with pytest.raises(nn.NNError):
+        srv.fetch(99, 32, nn.NN_F32)
+    srv.release(5)
+    with pytest.raises(nn.NNError):
+        srv.release(5)
+    srv.close()
