@@ -1,6 +1,7 @@
 """Benchmark of the NN inversion on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu] [--no-extras]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
+                    [--no-extras | --legs fp32,batched,mixed,serving]
 
 A step is one whole inversion through the C ABI: start-iterate prologue, then
 nests of d + 1 GEMMs until rms = ||I - A X||_F / sqrt(N) < tol.  The headline
@@ -10,8 +11,16 @@ synthetic and seeded, resident in HBM before the timed region.
 
 The JSON line carries the whole-job rate (inverses/s), the GEMM roofline
 (average GEMM launch duration from HIP events recorded by the library on its
-stream during the timed steps, against the FP64 MFMA peak), the oracle timed
-on the host on a bounded sample, and extra workloads under "extra".
+stream during the timed steps, against the FP64 MFMA peak; HBM traffic per
+launch from the committed counter summary when it was taken on the current
+GEMM source), the oracle timed on the host on a bounded sample, and under
+"extra" the other workloads:
+  fp32     the headline matrix in FP32 (runs to its rounding floor);
+  batched  4096 complex64 massive-MIMO Gram matrices, one graph launch;
+  mixed    N=16384 cond 1e4: BF16/FP32/FP64 schedule vs plain FP64 at the
+           same tolerance;
+  serving  a Poisson request stream through the continuous-batching server,
+           p50/p99 latency and inverses/s, against plain FP64 one by one.
 """
 import argparse
 import json
@@ -40,7 +49,38 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--legs", default="fp32,batched,mixed,serving",
+                    help="comma list of extra workloads to run")
+    ap.add_argument("--mixed-n", type=int, default=16384)
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=192)
+    ap.add_argument("--host-input", action="store_true",
+                    help="build the headline matrix with host (NumPy) QR only, no GPU library "
+                         "kernels before the NN launches (for counter collection)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run three plain 1 GiB device copies (untimed), the reference "
+                         "kernel for scaling HBM counters")
     return ap.parse_args()
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gemm_f64_n8192_traffic.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2212_02406_amd", "csrc", "nn_gemm.hip")
+
+
+def traffic_per_launch(n):
+    """HBM bytes per FP64 GEMM launch from the committed counter summary, or
+    None when it is missing, for another size, or was taken on another
+    revision of the GEMM source."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+        rec = json.loads(next(l[len("json: "):] for l in lines if l.startswith("json: ")))
+        sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("gemm_source_sha256") != sha or rec.get("n") != n:
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def time_inversions(nn, torch, A, steps, warmup, **kw):
@@ -109,6 +149,177 @@ def cpu_baseline(A_h, depth, iters):
                        f"({per_inverse:.1f} s per inverse)")}
 
 
+def leg_batched(nn, torch, workloads, np):
+    """4096 massive-MIMO Gram matrices G = H^H H + 0.1 I (H 128 x K, K in
+    {8,16,32,64}), complex64, depth 2, 4 fixed nests, one graph launch."""
+    packed, offsets, sizes, mats = workloads.mimo_gram_batch(batch=4096, seed=3)
+    P = torch.from_numpy(packed).cuda()
+    O = torch.from_numpy(offsets).cuda()
+    S = torch.from_numpy(sizes).cuda()
+    best_ms, wk, wg = nn.batched_autotune(P, O, S, 64, fixed_iter=4)
+    log(f"batched autotune: best {best_ms:.3f} ms wave_max_k={wk} wg_per_cu={wg}")
+    X = torch.empty_like(P)
+    info = torch.empty(4096 * 16, dtype=torch.uint8, device="cuda")
+    hold = nn.workspace(nn.nn_batched_workspace_size(4096, nn.NN_C64), P.device)
+    out = {}
+    for x0 in ("transpose", "identity"):
+        for _ in range(3):
+            nn.invert_batched(P, O, S, 64, x0=x0, fixed_iter=4, X=X, info=info, ws=hold)
+        torch.cuda.synchronize()
+        reps = 50
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            nn.invert_batched(P, O, S, 64, x0=x0, fixed_iter=4, X=X, info=info, ws=hold)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        it, st, rms = nn.decode_batched_info(info)
+        K = sizes.astype(np.float64)
+        flop = float(np.sum((4 * 3 + 1) * 8.0 * K ** 3))  # (k(d+1)+1) complex products
+        byts = float(np.sum(2 * 8.0 * K ** 2))  # read A, write X (complex64)
+        rms_by_k = {int(k): float(np.median(rms[sizes == k])) for k in (8, 16, 32, 64)}
+        out[x0] = {"ms_per_batch": ms, "inverses_per_s": 4096 / (ms / 1e3),
+                   "tflops": flop / (ms / 1e3) / 1e12, "gb_per_s": byts / (ms / 1e3) / 1e9,
+                   "frac_fp32_vector_peak": flop / (ms / 1e3) / 1e12 / PEAK_TFLOPS["f32"],
+                   "frac_hbm_peak": byts / (ms / 1e3) / 1e9 / 8000.0,
+                   "all_ok": bool(np.all(st == 0)), "median_rms_by_K": rms_by_k}
+        log(f"batched {x0}: {out[x0]}")
+    out["autotune"] = {"best_ms": best_ms, "wave_max_k": wk, "wg_per_cu": wg}
+    out["workload"] = ("4096 complex64 MIMO Gram matrices, M=128, K uniform in {8,16,32,64}, "
+                       "sigma2=0.1, depth 2, 4 fixed nests, seed 3")
+    return out
+
+
+def leg_mixed(nn, torch, workloads, np, n):
+    """Dense SPD N=16384, cond 1e4 (log-uniform spectrum), depth 2, scaled
+    identity start, tol 1e-11: mixed BF16/FP32/FP64 schedule vs plain FP64."""
+    A_h, lam, Q = workloads.dense_spd(n, 1.0, 1e4, 4, log_spectrum=True, device="cuda",
+                                      return_factors=True)
+    A = torch.from_numpy(A_h).cuda()
+    torch.cuda.synchronize()
+    res = {}
+    Xs = {}
+    for label, kw in (("mixed", dict(prec="mixed")), ("plain_fp64", dict(prec="plain"))):
+        X, info = nn.invert(A, depth=2, x0="identity", tol=1e-11, max_iter=100, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = nn.invert(A, depth=2, x0="identity", tol=1e-11, max_iter=100, X=X, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        Xs[label] = X
+        ph = info["phase_iters"]
+        flop = 2.0 * n ** 3 * info["gemms"]
+        if label == "mixed":
+            # each phase's products against its own peak; the rest of the
+            # products (switch residuals, the final residual) against FP64
+            per = 2.0 * n ** 3
+            nb, nf = ph[0] * 3, ph[1] * 3
+            nd = info["gemms"] - nb - nf
+            ideal = per * (nb / PEAK_TFLOPS["bf16"] + nf / PEAK_TFLOPS["f32"] +
+                           nd / PEAK_TFLOPS["f64"]) / 1e12
+        else:
+            ideal = flop / PEAK_TFLOPS["f64"] / 1e12
+        res[label] = {"s": t, "inverses_per_s": 1.0 / t, "status": info["status"],
+                      "iters": info["iters"], "phase_iters_bf16_fp32_fp64": ph,
+                      "rms": info["rms"], "gemms": info["gemms"],
+                      "tflops": flop / t / 1e12, "roofline_frac_phase_weighted": ideal / t}
+        log(f"mixed leg {label}: {res[label]}")
+    diff = (torch.linalg.norm(Xs["mixed"] - Xs["plain_fp64"]) /
+            torch.linalg.norm(Xs["plain_fp64"])).item()
+    X_h = Xs["mixed"].cpu().numpy()
+    cols = list(np.random.default_rng(1).choice(n, 4, replace=False))
+    err, resid = sampled_check(A_h, X_h, lam, Q, cols)
+    res["speedup_vs_plain_fp64"] = res["plain_fp64"]["s"] / res["mixed"]["s"]
+    res["rel_fro_diff_mixed_vs_plain_fp64"] = diff
+    res["mixed_sampled_rel_err_vs_exact_inverse_col"] = err
+    res["workload"] = (f"dense SPD N={n}, spectrum log-uniform [1,1e4] (cond 1e4), depth 2, "
+                       "scaled identity start, tol rms 1e-11, seed 4")
+    return res
+
+
+def leg_serving(nn, torch, workloads, np, pool_size, n_req):
+    """Poisson request stream over a pool of FP32 SPD / complex64 HPD
+    matrices, N log-uniform in [32, 4096], cond log-uniform in [10, 1e4],
+    tol 1e-4 or 1e-8: closed-loop capacity, open loop at 2000 req/s and at
+    half the capacity, and the same requests run one by one through plain
+    FP64 nn_invert."""
+    pool = workloads.serving_pool(pool_size, seed=5)
+    mats = []
+    for e in pool:
+        mats.append(torch.from_numpy(workloads.build_request(
+            e, device="cuda" if e["n"] >= 512 else None)).cuda())
+    torch.cuda.synchronize()
+    g = workloads.rng(55)
+    picks = g.integers(0, pool_size, n_req)
+    tols = [pool[i]["tol"] for i in picks]
+    d = 2
+
+    def flop_of(rec):
+        f = (rec["iters"] * (d + 1) + 1) * 2.0 * rec["n"] ** 3
+        return f * (4 if pool[picks[rec["id"]]]["complex"] else 1)
+
+    def run(rate):
+        srv = nn.Server(96 << 30, depth=d, max_active=512, n_streams=4)
+        srv.submit(-1, mats[0], 1e-4)
+        srv.run_until_idle()
+        srv.release(-1)
+        arr = np.zeros(n_req) if rate is None else np.cumsum(g.exponential(1.0 / rate, n_req))
+        t0 = time.perf_counter()
+        nxt, lat, recs = 0, {}, []
+        while len(lat) < n_req:
+            now = time.perf_counter() - t0
+            while nxt < n_req and arr[nxt] <= now:
+                srv.submit(nxt, mats[picks[nxt]], tols[nxt], 100)
+                nxt += 1
+            s = srv.tick()
+            for r in srv.poll():
+                if r["status"] >= 0:
+                    srv.fetch(r["id"], r["n"], r["out_dtype"], out_device="cpu")
+                else:
+                    srv.release(r["id"])
+                lat[r["id"]] = time.perf_counter() - t0 - arr[r["id"]]
+                recs.append(r)
+            if s.active == 0 and s.queued == 0 and nxt < n_req:
+                time.sleep(max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 1e-3)))
+        wall = time.perf_counter() - t0
+        srv.close()
+        L = np.array([lat[i] for i in range(n_req)])
+        ok = sum(1 for r in recs if r["status"] == 0)
+        return {"offered_req_per_s": rate, "requests": n_req, "wall_s": wall,
+                "inverses_per_s": n_req / wall, "p50_ms": 1e3 * float(np.percentile(L, 50)),
+                "p99_ms": 1e3 * float(np.percentile(L, 99)),
+                "tflops": sum(flop_of(r) for r in recs) / wall / 1e12,
+                "ok": ok, "promoted_to_fp64": sum(1 for r in recs if r["wide_iters"] > 0),
+                "max_rms_over_tol_ok": max([r["rms"] / tols[r["id"]] for r in recs
+                                            if r["status"] == 0], default=None)}
+
+    out = {"capacity_closed_loop": run(None)}
+    log(f"serving capacity: {out['capacity_closed_loop']}")
+    out["open_loop_2000"] = run(2000.0)
+    log(f"serving 2000 req/s: {out['open_loop_2000']}")
+    half = 0.5 * out["capacity_closed_loop"]["inverses_per_s"]
+    out["open_loop_half_capacity"] = run(half)
+    log(f"serving {half:.0f} req/s: {out['open_loop_half_capacity']}")
+    # the same requests one by one through plain FP64 nn_invert
+    wide = {}
+    for i in set(int(x) for x in picks):
+        wide[i] = mats[i].to(torch.complex128 if mats[i].is_complex() else torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r, i in enumerate(picks):
+        nn.invert(wide[int(i)], depth=d, x0="identity", tol=tols[r], max_iter=100)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["plain_fp64_sequential"] = {"wall_s": t, "inverses_per_s": n_req / t}
+    out["served_vs_plain_fp64"] = out["capacity_closed_loop"]["inverses_per_s"] / (n_req / t)
+    out["workload"] = (f"{n_req} requests drawn from a pool of {pool_size} (seed 5): FP32 SPD or "
+                       "complex64 HPD 50/50, N log-uniform [32,4096], cond log-uniform [10,1e4], "
+                       "tol 1e-4 or 1e-8 50/50; depth 2, scaled identity start; latency = "
+                       "arrival to result in host memory")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -121,11 +332,21 @@ def main():
 
     n, d = args.n, args.depth
     log(f"generating dense SPD n={n} (cond 1e3, log-uniform spectrum, seed 2)")
-    A_h, lam, Q = workloads.dense_spd(n, 1.0, 1e3, 2, log_spectrum=True,
-                                      device="cuda" if n >= 2048 else None, return_factors=True)
+    gen_dev = "cuda" if n >= 2048 and not args.host_input else None
+    A_h, lam, Q = workloads.dense_spd(n, 1.0, 1e3, 2, log_spectrum=True, device=gen_dev,
+                                      return_factors=True)
     A = torch.from_numpy(A_h).to("cuda:0")
     torch.cuda.synchronize()
     log("input resident in HBM")
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x 1 GiB device copies done")
 
     X, infos, secs = time_inversions(nn, torch, A, args.steps, args.warmup, depth=d,
                                      x0="transpose", tol=1e-12, max_iter=100)
@@ -157,12 +378,15 @@ def main():
                   "max_residual_col_norm": res},
         "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,8,2,4,2,2,false>",
                      "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f64"], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS["f64"], "traffic": traffic_per_launch(n),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": 3 * 8 * n * n,
                      "per_launch_flop": flop_gemm, "avg_launch_ms": avg_gemm_s * 1e3},
     }
 
     extra = {}
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(args.legs.split(","))
+    if "fp32" in legs:
         A32 = A.to(torch.float32)
         X32, i32, s32 = time_inversions(nn, torch, A32, 1, 1, depth=d, x0="transpose", tol=1e-6,
                                         max_iter=100)
@@ -176,6 +400,17 @@ def main():
                          "note": "tol 1e-6 is below the FP32 rounding floor; runs to STAGNATED"}
         log(f"fp32: {extra['fp32']}")
         del A32, X32
+    if legs & {"batched", "mixed", "serving"}:
+        del X
+        torch.cuda.empty_cache()
+    if "batched" in legs:
+        extra["batched"] = leg_batched(nn, torch, workloads, np)
+    if "mixed" in legs:
+        extra["mixed"] = leg_mixed(nn, torch, workloads, np, args.mixed_n)
+        torch.cuda.empty_cache()
+    if "serving" in legs:
+        extra["serving"] = leg_serving(nn, torch, workloads, np, args.serve_pool,
+                                       args.serve_requests)
     out["extra"] = extra
 
     if not args.no_cpu:
