@@ -76,8 +76,30 @@ __device__ __forceinline__ T& lane_of(typename VecOf<T, V>::type& v, int e) {
 
 constexpr int kGroupM = 8;
 
+// Padding (elements) of a Bs row.  The four lane groups of a B fragment read
+// rows KQ apart; the row offset between consecutive groups is placed half the
+// 64 banks away for 8-byte elements (a 64-lane ds_read_b64 is served 32 lanes
+// at a time) and a quarter away for 4-byte elements (64 lanes at once), so the
+// groups do not collide.  Rows stay 16-byte multiples for the vector stores.
+constexpr int pick_padb(int bn, int kq, int esz) {
+  const int words = esz / 4, target = esz == 8 ? 32 : 16, step = 16 / esz;
+  for (int p = step; p < 64; p += step)
+    if ((kq * (bn + p) * words) % 64 == target) return p;
+  return step;
+}
+
 // Source of the zeros loaded for out-of-range elements (read only).
 __device__ __attribute__((aligned(16))) const double kZero16[2] = {0.0, 0.0};
+
+// Load from global memory through an address-space-1 pointer.  The operand
+// addresses are chosen by a select between the matrix and kZero16; without
+// the cast the compiler emits flat loads, which also count against the LDS
+// wait counter, so every wait for the LDS fragment reads would wait for the
+// global prefetch as well.
+template <typename V>
+__device__ __forceinline__ V load_global(uintptr_t addr) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) V*>(addr);
+}
 
 __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
   const int q = nwg / kNumXcd, r = nwg % kNumXcd;
@@ -102,8 +124,11 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
   constexpr int PAD = 16 / (int)sizeof(T);
-  constexpr int LAS = BK + PAD;  // As row stride ([m][k] layout)
-  constexpr int LBS = BN + PAD;  // Bs row stride ([k][n] layout)
+  constexpr int KQ = BK / 4;     // k values per lane and slab (see compute)
+  constexpr int LAS = BK + PAD;  // As row stride ([m][k] layout), 16-byte multiple
+  // Bs row stride ([k][n] layout): lane groups read rows KQ apart, padded so
+  // the four groups of a fragment read land in different banks
+  constexpr int LBS = BN + pick_padb(BN, KQ, (int)sizeof(T));
   constexpr int A_VPR = BK / VEC, B_VPR = BN / VEC;
   // vectors per slab, and per thread (the last round may cover only some
   // waves when a slab holds fewer vectors than the workgroup has threads)
@@ -143,7 +168,7 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
   // current slab's MFMAs (the loads stay in flight across the compute).  The
   // vector path is chosen by the host only when K, N and the leading
   // dimensions are multiples of VEC, so a vector is wholly in or out.
-  const T* __restrict__ zsrc = reinterpret_cast<const T*>(kZero16);
+  const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZero16);
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
@@ -152,7 +177,8 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
       const int r = v / A_VPR, c = (v % A_VPR) * VEC;
       const int64_t gr = m0 + r, gc = k0 + c;
       const bool ok = gr < M && gc < K;
-      ra[i] = *reinterpret_cast<const vec_t*>(ok ? A + gr * p.lda + gc : zsrc);
+      const uintptr_t src = reinterpret_cast<uintptr_t>(A + gr * p.lda + gc);
+      ra[i] = load_global<vec_t>(ok ? src : zaddr);
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
@@ -162,7 +188,8 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
       const int64_t gr = k0 + r, gc = n0 + c;
       const int64_t srow = CPLX ? (gr >> 1) : gr;
       const bool ok = gr < K && gc < N;
-      rb[i] = *reinterpret_cast<const vec_t*>(ok ? B + srow * p.ldb + gc : zsrc);
+      const uintptr_t src = reinterpret_cast<uintptr_t>(B + srow * p.ldb + gc);
+      rb[i] = load_global<vec_t>(ok ? src : zaddr);
     }
   };
 
@@ -196,21 +223,28 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
     }
   };
 
+  // k order inside a slab: at MFMA step kk, lane group lk = lane / 16
+  // supplies k = lk * KQ + kk (for A and B alike, so every k of the slab is
+  // summed once).  A lane's A operands of the whole slab are then KQ
+  // consecutive elements of one LDS row: one wide read per fragment.
+  using kvec_t = typename VecOf<T, KQ>::type;
   const int lr = lane & 15, lk = lane >> 4;
   auto compute = [&](int buf) {
-    const T* as = As[buf] + (wm * WTM + lr) * LAS + lk;
-    const T* bs = Bs[buf] + lk * LBS + wn * WTN + lr;
+    const T* as = As[buf] + (wm * WTM + lr) * LAS + lk * KQ;
+    const T* bs = Bs[buf] + lk * KQ * LBS + wn * WTN + lr;
+    kvec_t av[FM];
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      T af[FM], bf[FN];
+    for (int i = 0; i < FM; ++i) av[i] = *reinterpret_cast<const kvec_t*>(as + i * 16 * LAS);
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = as[i * 16 * LAS + kk * 4];
+    for (int kk = 0; kk < KQ; ++kk) {
+      T bf[FN];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = bs[kk * 4 * LBS + j * 16];
+      for (int j = 0; j < FN; ++j) bf[j] = bs[kk * LBS + j * 16];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = Mfma<T>::run(lane_of<T, KQ>(av[i], kk), bf[j], acc[i][j]);
     }
   };
 

@@ -37,6 +37,13 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 
 __device__ __attribute__((aligned(16))) const unsigned int kZeroBf16[4] = {0u, 0u, 0u, 0u};
 
+// Global loads through an address-space-1 pointer (a select between the
+// matrix and kZeroBf16 otherwise becomes a flat load, which the LDS wait
+// counter also tracks).
+__device__ __forceinline__ u4_t load_global(uintptr_t addr) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) u4_t*>(addr);
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
   const int q = nwg / kNumXcd, r = nwg % kNumXcd;
   const int x = bid % kNumXcd, local = bid / kNumXcd;
@@ -69,7 +76,7 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
 
   // 128 rows x 64 k per operand and slab = 1024 16-byte vectors, 4 per thread
   u4_t ra[4], rb[4];
-  const uint16_t* zsrc = reinterpret_cast<const uint16_t*>(kZeroBf16);
+  const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZeroBf16);
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -77,8 +84,10 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
       const int r = v >> 3, c = (v & 7) * 8;
       const int64_t gk = k0 + c;
       const int64_t ga = m0 + r, gb = n0 + r;
-      ra[i] = *reinterpret_cast<const u4_t*>((ga < p.M && gk < p.K) ? A + ga * p.lda + gk : zsrc);
-      rb[i] = *reinterpret_cast<const u4_t*>((gb < p.N && gk < p.K) ? Bt + gb * p.ldb + gk : zsrc);
+      const uintptr_t sa = reinterpret_cast<uintptr_t>(A + ga * p.lda + gk);
+      const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
+      ra[i] = load_global((ga < p.M && gk < p.K) ? sa : zaddr);
+      rb[i] = load_global((gb < p.N && gk < p.K) ? sb : zaddr);
     }
   };
   auto sstore = [&](int buf) {
@@ -121,7 +130,10 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
   __syncthreads();
   for (int kt = 0; kt < nk - 1; ++kt) {
     gload((int64_t)(kt + 1) * BK);
+    // issue the global loads first and keep the LDS stores after all MFMAs
+    __builtin_amdgcn_sched_barrier(0);
     compute(kt & 1);
+    __builtin_amdgcn_sched_barrier(0);
     sstore((kt + 1) & 1);
     __syncthreads();
   }
