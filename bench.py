@@ -376,7 +376,7 @@ def main():
         "gemms_per_inverse": info["gemms"],
         "check": {"sampled_cols": len(cols), "max_rel_err_vs_exact_inverse_col": err,
                   "max_residual_col_norm": res},
-        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,8,2,4,2,2,false>",
+        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,16,2,4,2,2,false,true>",
                      "achieved": achieved, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f64"], "traffic": traffic_per_launch(n),
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",

@@ -50,6 +50,8 @@ __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
   return x * q + (x < r ? x : r) + local;
 }
 
+// EXACT: M, N multiples of 128 and K of 64 (no bounds checks anywhere).
+template <bool EXACT>
 __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDS_STRIDE];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDS_STRIDE];
@@ -77,17 +79,31 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
   // 128 rows x 64 k per operand and slab = 1024 16-byte vectors, 4 per thread
   u4_t ra[4], rb[4];
   const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZeroBf16);
+  // exact tiling: wave-uniform slab base plus a fixed 32-bit offset per load
+  const int r0 = tid >> 3, c0 = (tid & 7) * 8;  // row r0 + 32 i of the slab
+  const uint32_t oa = (uint32_t)(r0 * p.lda + c0), ob = (uint32_t)(r0 * p.ldb + c0);
+  const uint32_t sa32 = (uint32_t)(32 * p.lda), sb32 = (uint32_t)(32 * p.ldb);
   auto gload = [&](int64_t k0) {
+    if constexpr (EXACT) {
+      const uint16_t* a0 = A + m0 * p.lda + k0;
+      const uint16_t* b0 = Bt + n0 * p.ldb + k0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int v = tid + i * NT;
-      const int r = v >> 3, c = (v & 7) * 8;
-      const int64_t gk = k0 + c;
-      const int64_t ga = m0 + r, gb = n0 + r;
-      const uintptr_t sa = reinterpret_cast<uintptr_t>(A + ga * p.lda + gk);
-      const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
-      ra[i] = load_global((ga < p.M && gk < p.K) ? sa : zaddr);
-      rb[i] = load_global((gb < p.N && gk < p.K) ? sb : zaddr);
+      for (int i = 0; i < 4; ++i) {
+        ra[i] = load_global(reinterpret_cast<uintptr_t>(a0 + (oa + i * sa32)));
+        rb[i] = load_global(reinterpret_cast<uintptr_t>(b0 + (ob + i * sb32)));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int v = tid + i * NT;
+        const int r = v >> 3, c = (v & 7) * 8;
+        const int64_t gk = k0 + c;
+        const int64_t ga = m0 + r, gb = n0 + r;
+        const uintptr_t sa = reinterpret_cast<uintptr_t>(A + ga * p.lda + gk);
+        const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
+        ra[i] = load_global((ga < p.M && gk < p.K) ? sa : zaddr);
+        rb[i] = load_global((gb < p.N && gk < p.K) ? sb : zaddr);
+      }
     }
   };
   auto sstore = [&](int buf) {
@@ -152,7 +168,7 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
       for (int t = 0; t < 4; ++t) {
         const int64_t r = rbase + t;
         float v = 0.f;
-        if (r < p.M && c < p.N) {
+        if (EXACT || (r < p.M && c < p.N)) {
           v = alpha * acc[i][j][t];
           if (p.E) v += p.E[r * p.lde + c];
           if (r == c) v += diag;
@@ -162,11 +178,11 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
         }
         tb[t] = to_bf16(v);
       }
-      if (p.CbfT && c < p.N) {
+      if (p.CbfT && (EXACT || c < p.N)) {
         // C^T[c][rbase .. rbase + 3]: four consecutive bf16 of one transposed row
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-          if (rbase + t < p.M) p.CbfT[c * p.ldct + rbase + t] = tb[t];
+          if (EXACT || rbase + t < p.M) p.CbfT[c * p.ldct + rbase + t] = tb[t];
       }
     }
   }
@@ -217,7 +233,12 @@ GemmPlan plan_gemm_bf16(int64_t M, int64_t N) {
 hipError_t launch_gemm_bf16(const GemmPlan& plan, const Bf16GemmArgs& a, hipStream_t s) {
   const int grid = plan.num_tiles();
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(grid), dim3(NT), 0, s, a, plan.tiles_m, plan.tiles_n);
+  if (a.M % BM == 0 && a.N % BN == 0 && a.K % BK == 0)
+    hipLaunchKernelGGL(gemm_bf16_kernel<true>, dim3(grid), dim3(NT), 0, s, a, plan.tiles_m,
+                       plan.tiles_n);
+  else
+    hipLaunchKernelGGL(gemm_bf16_kernel<false>, dim3(grid), dim3(NT), 0, s, a, plan.tiles_m,
+                       plan.tiles_n);
   return hipGetLastError();
 }
 
