@@ -185,6 +185,22 @@ def leg_batched(nn, torch, workloads, np):
                    "frac_hbm_peak": byts / (ms / 1e3) / 1e9 / 8000.0,
                    "all_ok": bool(np.all(st == 0)), "median_rms_by_K": rms_by_k}
         log(f"batched {x0}: {out[x0]}")
+    # the same matrices one by one through plain FP64 (complex128) nn_invert,
+    # 4 fixed nests each: every 16th matrix of the batch, scaled to the batch
+    sample = list(range(0, 4096, 16))
+    wide = [torch.from_numpy(mats[b].astype(np.complex128)).cuda() for b in sample]
+    for Mt in wide[:4]:
+        nn.invert(Mt, depth=2, x0="transpose", fixed_iter=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for Mt in wide:
+        nn.invert(Mt, depth=2, x0="transpose", fixed_iter=4)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / len(sample)
+    out["plain_fp64_one_by_one"] = {"s_per_matrix": per, "inverses_per_s": 1.0 / per,
+                                    "sample": f"{len(sample)} matrices (every 16th)"}
+    out["batched_vs_plain_fp64"] = out["transpose"]["inverses_per_s"] * per
+    log(f"batched vs plain fp64 one by one: {out['batched_vs_plain_fp64']:.0f}x")
     out["autotune"] = {"best_ms": best_ms, "wave_max_k": wk, "wg_per_cu": wg}
     out["workload"] = ("4096 complex64 MIMO Gram matrices, M=128, K uniform in {8,16,32,64}, "
                        "sigma2=0.1, depth 2, 4 fixed nests, seed 3")

@@ -90,19 +90,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 typedef float f2_t __attribute__((ext_vector_type(2)));
 
-// Operands of one k-group (16 real k) for NB output blocks.
-template <bool CPLX, int NB>
+// Operands of one k-group (16 real k) for NB output blocks.  SH: the NB
+// blocks of a wave lie in one block row and share their A fragment.
+template <bool CPLX, int NB, bool SH>
 struct KFrag {
-  f4_t a[NB];
+  f4_t a[SH ? 1 : NB];
   f4_t b[NB];  // complex: (p0.x, p0.y, p1.x, p1.y); real: 4 rows of B
 };
 
-template <bool CPLX, int NB>
-__device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB>& f, const int* aoff, const int* boff,
-                                            int j, int ld) {
+template <bool CPLX, int NB, bool SH>
+__device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB, SH>& f, const int* aoff,
+                                            const int* boff, int j, int ld) {
+#pragma unroll
+  for (int i = 0; i < (SH ? 1 : NB); ++i)
+    f.a[i] = *reinterpret_cast<const f4_t*>(&smem[aoff[i] + 16 * j]);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    f.a[i] = *reinterpret_cast<const f4_t*>(&smem[aoff[i] + 16 * j]);
     if constexpr (CPLX) {
       const int o = boff[i] + 8 * j * ld;
       const f2_t p0 = *reinterpret_cast<const f2_t*>(&smem[o]);
@@ -115,10 +118,12 @@ __device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB>& f, const int* aoff,
   }
 }
 
-template <bool CPLX, int NB>
-__device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB>& f, const bool* even) {
+template <bool CPLX, int NB, bool SH>
+__device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB, SH>& f,
+                                           const bool* even) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
+    const f4_t a = f.a[SH ? 0 : i];
     float b0, b1, b2, b3;
     if constexpr (CPLX) {
       // expanded rows 2 kc, 2 kc + 1 of two complex rows kc0, kc0 + 1
@@ -133,10 +138,10 @@ __device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB>& f, 
       b2 = f.b[i].z;
       b3 = f.b[i].w;
     }
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].x, b0, acc[i], 0, 0, 0);
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].y, b1, acc[i], 0, 0, 0);
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].z, b2, acc[i], 0, 0, 0);
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i].w, b3, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b0, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b1, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b2, acc[i], 0, 0, 0);
+    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b3, acc[i], 0, 0, 0);
   }
 }
 
@@ -152,8 +157,11 @@ __device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB>& f, 
 // a lane's four A values of the group are contiguous (one 16-byte read).  For
 // a complex B the four k are the rows 2 kc, 2 kc + 1 of two complex rows, whose
 // expanded entries come from one 8-byte (re, im) read each.  All operand reads
-// of a k-group are issued before its MFMAs.
-template <bool CPLX, int NB>
+// of a k-group are issued before its MFMAs; when a wave's blocks share a block
+// row (SH) their A fragment is read once.  (Reading k-group j + 1 during the
+// MFMAs of k-group j needs a second register set, which made the compiler
+// spill in this fully inlined kernel.)
+template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, int ld,
                                             float alpha, float diag, const Group& g,
                                             double* ss) {
@@ -183,9 +191,9 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
   }
   const int kgroups = nbn;  // padded real inner dimension / 16
   for (int j = 0; j < kgroups; ++j) {
-    KFrag<CPLX, NB> f;
-    load_kgroup<CPLX, NB>(f, aoff, boff, j, ld);  // all operand reads of the group first
-    mma_kgroup<CPLX, NB>(acc, f, even);
+    KFrag<CPLX, NB, SH> f;
+    load_kgroup<CPLX, NB, SH>(f, aoff, boff, j, ld);  // all operand reads of the group first
+    mma_kgroup<CPLX, NB, SH>(acc, f, even);
   }
   // Epilogue in registers (rows 4 (lane/16) + t of each block, FP32 layout).
   double s = 0.0;
@@ -237,9 +245,16 @@ __device__ __forceinline__ int blocks_per_wave(int K, bool cplx, int G) {
   return per <= 1 ? 1 : per <= 2 ? 2 : per <= 4 ? 4 : 8;
 }
 
+// Whether the NB blocks of each wave lie in one block row (NB divides the
+// number of column blocks), so they can share one A fragment per k-group.
+__device__ __forceinline__ bool shared_rows(int K, bool cplx, int NB) {
+  const int nbn = ((cplx ? 2 * K : K) + 15) >> 4;
+  return nbn % NB == 0;
+}
+
 // The whole NN run for one matrix: load, start iterate, `iters` nests of
 // depth d, final residual, store.
-template <bool CPLX, int NB>
+template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, int depth, int x0,
                                            int iters,
                            int buf, int bufstride, const Group& g, nn_info_dev* info) {
@@ -312,16 +327,16 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   }
   g.sync();
   for (int it = 0; it < iters; ++it) {
-    lds_gemm_nb<CPLX, NB>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, nullptr);  // R = I - G X
+    lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, nullptr);  // R = I - G X
     int U = Rs;
     for (int m = 1; m < depth; ++m) {  // U_{m+1} = R + R U_m
-      lds_gemm_nb<CPLX, NB>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr);
+      lds_gemm_nb<CPLX, NB, SH>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr);
       U = Us;
     }
-    lds_gemm_nb<CPLX, NB>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
+    lds_gemm_nb<CPLX, NB, SH>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
   }
   double ss = 0.0;
-  lds_gemm_nb<CPLX, NB>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, &ss);
+  lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, &ss);
   const double rms = sqrt(ss / (double)K);
   for (int e = g.gtid; e < K * cols; e += nthr) {
     const int r = e / cols, c = e - r * cols;
@@ -416,12 +431,20 @@ __global__ void __launch_bounds__(kThreads) batched_nn(const float* A, float* X,
       const int64_t off = offsets[b] * cm;
       const int K = sizes[b];
       nn_info_dev* inf = info ? info + b : nullptr;
-      switch (blocks_per_wave(K, CPLX, 4)) {
-        case 1: invert_one<CPLX, 1>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
-        case 2: invert_one<CPLX, 2>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
-        case 4: invert_one<CPLX, 4>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
-        default: invert_one<CPLX, 8>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf); break;
+      const int nbw = blocks_per_wave(K, CPLX, 4);
+      const bool sh = shared_rows(K, CPLX, nbw);
+#define NN_ONE(NB, SH) invert_one<CPLX, NB, SH>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf)
+      switch (nbw * 2 + (sh ? 1 : 0)) {
+        case 2:
+        case 3: NN_ONE(1, true); break;  // one block per wave always shares its row
+        case 4: NN_ONE(2, false); break;
+        case 5: NN_ONE(2, true); break;
+        case 8: NN_ONE(4, false); break;
+        case 9: NN_ONE(4, true); break;
+        case 17: NN_ONE(8, true); break;
+        default: NN_ONE(8, false); break;
       }
+#undef NN_ONE
     } else {
       const int idx = n_large + 4 * (item - n_large) + wave;
       if (idx < n_large + n_small) {
@@ -431,12 +454,20 @@ __global__ void __launch_bounds__(kThreads) batched_nn(const float* A, float* X,
         const int K = sizes[b];
         const int base = wave * 4 * wave_stride;
         nn_info_dev* inf = info ? info + b : nullptr;
-        switch (blocks_per_wave(K, CPLX, 1)) {
-          case 1: invert_one<CPLX, 1>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
-          case 2: invert_one<CPLX, 2>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
-          case 4: invert_one<CPLX, 4>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
-          default: invert_one<CPLX, 8>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf); break;
+        const int nbw = blocks_per_wave(K, CPLX, 1);
+        const bool sh = shared_rows(K, CPLX, nbw);
+#define NN_ONE(NB, SH) invert_one<CPLX, NB, SH>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf)
+        switch (nbw * 2 + (sh ? 1 : 0)) {
+          case 2:
+          case 3: NN_ONE(1, true); break;  // one block per wave always shares its row
+          case 4: NN_ONE(2, false); break;
+          case 5: NN_ONE(2, true); break;
+          case 8: NN_ONE(4, false); break;
+          case 9: NN_ONE(4, true); break;
+          case 17: NN_ONE(8, true); break;
+          default: NN_ONE(8, false); break;
         }
+#undef NN_ONE
       }
     }
     __syncthreads();
