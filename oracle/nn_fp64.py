@@ -215,6 +215,95 @@ def nn_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
     return x, info
 
 
+def nn_factorized_solve_ref(A, B, x0: int = X0_TRANSPOSE, tol: float = 1e-10,
+                            max_factors: int = 60, fixed_factors: int | None = None):
+    """Solve A x = B with the factorised Neumann series applied to B, without
+    forming the inverse (Corollary 6 and the linear-solve form after it):
+
+        x = prod_{n=0}^{s-1} (I + P^(2^n)) phi B,   P = I - phi A,
+
+    which equals the truncated series sum_{n=0}^{2^s-1} P^n phi B.  phi is
+    the start of ``initial_guess`` (transpose or scaled identity).  Steps, in
+    the paper's order: phi and P; y_0 = phi B; factor n maps y_n to
+    y_{n+1} = (I + P^(2^n)) y_n, the power P^(2^n) being the square of
+    P^(2^(n-1)).
+
+    Control, for s = 0, 1, ... with rel_s = ||B - A y_s||_F / ||B||_F of
+    the iterate after s factors:
+      * fixed mode (fixed_factors given): exactly fixed_factors factors,
+        status OK unless rel is not finite;
+      * tolerance mode, in this order:
+          rel_s not finite                               -> ERR_NONFINITE
+          rel_s < tol                                    -> OK, y_s
+          s > 0, rel_s >= 1 and rel_s > rel_{s-1}        -> ERR_DIVERGED
+          s > 0, rel_{s-1} < 0.1 and rel_s >= rel_{s-1}  -> STAGNATED, y_{s-1}
+          s == max_factors                               -> NOT_CONVERGED, y_s
+      * before the loop: den not finite -> ERR_NONFINITE, den <= 0 ->
+        ERR_DIVERGED (as in nn_ref).
+    (For Hermitian A both starts make A P^m A^-1 Hermitian with eigenvalues
+    in [0, 1), so rel_s never increases in exact arithmetic: an increase in
+    the asymptotic regime is the rounding floor.)
+
+    Returns (x, info) with info = {"factors", "rel_residual", "status",
+    "trace", "den"}; the power P^(2^n) is formed only when factor n is
+    applied.
+    """
+    A = np.asarray(A)
+    B = np.asarray(B)
+    if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 1:
+        raise ValueError("A must be a non-empty square matrix")
+    if B.ndim != 2 or B.shape[0] != A.shape[0]:
+        raise ValueError("B must have A's row count")
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B)
+    dt = np.complex128 if cplx else np.float64
+    A = A.astype(dt)
+    B = B.astype(dt)
+    n = A.shape[0]
+    den, phi = initial_guess(A, x0)
+    info = {"factors": 0, "rel_residual": math.nan, "status": OK, "trace": [], "den": den}
+    if not math.isfinite(den):
+        info["status"] = ERR_NONFINITE
+        return phi @ B, info
+    if den <= 0.0:
+        info["status"] = ERR_DIVERGED
+        return phi @ B, info
+    P = np.eye(n, dtype=dt) - phi @ A
+    y = phi @ B
+    bnorm = float(np.linalg.norm(B))
+    Pk = None          # P^(2^(s-1)) once factor s-1 has been applied
+    y_prev, rel_prev = None, math.nan
+    s = 0
+    while True:
+        rel = float(np.linalg.norm(B - A @ y)) / bnorm if bnorm > 0 else 0.0
+        info["trace"].append(rel)
+        if fixed_factors is not None:
+            if s == fixed_factors:
+                info.update(factors=s, rel_residual=rel,
+                            status=OK if math.isfinite(rel) else ERR_NONFINITE)
+                return y, info
+        else:
+            if not math.isfinite(rel):
+                info.update(factors=s, rel_residual=rel, status=ERR_NONFINITE)
+                return y, info
+            if rel < tol:
+                info.update(factors=s, rel_residual=rel, status=OK)
+                return y, info
+            if s > 0 and rel >= 1.0 and rel > rel_prev:
+                info.update(factors=s, rel_residual=rel, status=ERR_DIVERGED)
+                return y, info
+            if s > 0 and rel_prev < 0.1 and rel >= rel_prev:
+                info.update(factors=s - 1, rel_residual=rel_prev, status=STAGNATED)
+                return y_prev, info
+            if s == max_factors:
+                info.update(factors=s, rel_residual=rel, status=NOT_CONVERGED)
+                return y, info
+        # factor s: (I + P^(2^s)) applied to y
+        Pk = P if Pk is None else Pk @ Pk
+        y_prev, rel_prev = y, rel
+        y = y + Pk @ y
+        s += 1
+
+
 def nn_batched_ref(mats, d: int = 2, x0: int = X0_TRANSPOSE, fixed_iter: int = 4):
     """The batched form: each matrix of ``mats`` independently, fixed nests.
 
