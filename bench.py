@@ -1,7 +1,7 @@
 """Benchmark of the NN inversion on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--no-extras | --legs fp32,batched,mixed,serving]
+                    [--no-extras | --legs fp32,factorized,batched,mixed,serving]
 
 A step is one whole inversion through the C ABI: start-iterate prologue, then
 nests of d + 1 GEMMs until rms = ||I - A X||_F / sqrt(N) < tol.  The headline
@@ -20,7 +20,9 @@ GEMM source), the oracle timed on the host on a bounded sample, and under
   mixed    N=16384 cond 1e4: BF16/FP32/FP64 schedule vs plain FP64 at the
            same tolerance;
   serving  a Poisson request stream through the continuous-batching server,
-           p50/p99 latency and inverses/s, against plain FP64 one by one.
+           p50/p99 latency and inverses/s, against plain FP64 one by one;
+  factorized  A X = B (64 right-hand sides) on the headline matrix with the
+           factorised series of Corollary 6, against nn_solve.
 """
 import argparse
 import json
@@ -49,7 +51,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp32,batched,mixed,serving",
+    ap.add_argument("--legs", default="fp32,factorized,batched,mixed,serving",
                     help="comma list of extra workloads to run")
     ap.add_argument("--mixed-n", type=int, default=16384)
     ap.add_argument("--serve-pool", type=int, default=64)
@@ -254,6 +256,31 @@ def leg_mixed(nn, torch, workloads, np, n):
     return res
 
 
+def leg_factorized(nn, torch, workloads, np, A, n):
+    """A X = B for the headline matrix and 64 right-hand sides: the
+    factorised series of Corollary 6 applied to B (relative residual 1e-7,
+    above its FP64 floor of ~3e-8 on this matrix) against nn_solve (the NN
+    inverse to rms 1e-8, then X B), both from the transpose start."""
+    B = torch.from_numpy(workloads.rng(9).standard_normal((n, 64))).cuda()
+    out = {}
+    for label, fn in (("factorized", lambda: nn.solve_factorized(A, B, x0="transpose", tol=1e-7)),
+                      ("nn_solve", lambda: nn.solve(A, B, depth=2, x0="transpose", tol=1e-8))):
+        X, info = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[label] = {"s": t, "solves_per_s": 1.0 / t, "status": info["status"],
+                      "iters": info["iters"], "gemms": info["gemms"],
+                      "rel_residual": info["rel_residual"]}
+        log(f"factorized leg {label}: {out[label]}")
+    out["speedup_vs_nn_solve"] = out["nn_solve"]["s"] / out["factorized"]["s"]
+    out["workload"] = (f"dense SPD N={n} FP64 cond 1e3 (the headline matrix), 64 right-hand "
+                       "sides N(0,1) seed 9, transpose start")
+    return out
+
+
 def leg_serving(nn, torch, workloads, np, pool_size, n_req):
     """Poisson request stream over a pool of FP32 SPD / complex64 HPD
     matrices, N log-uniform in [32, 4096], cond log-uniform in [10, 1e4],
@@ -416,6 +443,8 @@ def main():
                          "note": "tol 1e-6 is below the FP32 rounding floor; runs to STAGNATED"}
         log(f"fp32: {extra['fp32']}")
         del A32, X32
+    if "factorized" in legs:
+        extra["factorized"] = leg_factorized(nn, torch, workloads, np, A, n)
     if legs & {"batched", "mixed", "serving"}:
         del X
         torch.cuda.empty_cache()

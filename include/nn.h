@@ -161,6 +161,35 @@ nn_status nn_solve(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64
                    const nn_params* params, void* ws, size_t ws_bytes, nn_info* info,
                    double* rel_residual);
 
+/* Workspace bytes nn_solve_factorized needs (0 on bad arguments). */
+size_t nn_solve_factorized_workspace_size(int64_t n, int64_t nrhs, nn_dtype dtype,
+                                          const nn_params* params);
+
+/* Solve A Xsol = B with the factorised Neumann series applied to B, without
+ * forming the inverse (Corollary 6 and the linear-solve form after it):
+ *     Xsol = prod_{n=0}^{s-1} (I + P^(2^n)) phi B,   P = I - phi A,
+ * the truncated series sum_{n < 2^s} P^n phi B (= s Newton nests applied to
+ * B).  phi is the start X_0 of params->x0 (NN_X0_TRANSPOSE: any nonsingular
+ * A; NN_X0_SCALED_IDENTITY: Hermitian PD A; NN_X0_GIVEN is not supported).
+ * Per factor: one n x n x n product (the square P^(2^n), formed only when the
+ * factor is applied) and two n x n x nrhs products (the factor and the
+ * residual B - A Xsol).
+ *   params->fixed_iter > 0: exactly that many factors, one host
+ *     synchronisation at the end; else tolerance mode on the relative
+ *     residual ||B - A Xsol||_F / ||B||_F with tol, at most max_iter factors
+ *     (<= 62), and the status rules of nn_invert (stagnation: the previous
+ *     residual below 0.1 and no decrease; then the previous iterate is
+ *     returned).  depth is ignored; prec must be NN_PREC_PLAIN.
+ *   info->iters = factors applied, info->rms = relative residual of the
+ *     returned Xsol (also written to *rel_residual if non-NULL), the trace
+ *     holds the relative residual after 0, 1, ... factors.
+ * B (n x nrhs, ldb) and Xsol (n x nrhs, ldx) are device arrays; Xsol must
+ * not alias A or B. */
+nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const void* B,
+                              int64_t ldb, void* Xsol, int64_t ldx, int64_t n, int64_t nrhs,
+                              nn_dtype dtype, const nn_params* params, void* ws,
+                              size_t ws_bytes, nn_info* info, double* rel_residual);
+
 /* Workspace bytes nn_invert_batched needs for `batch` matrices. */
 size_t nn_batched_workspace_size(int32_t batch, nn_dtype dtype);
 

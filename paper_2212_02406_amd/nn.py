@@ -95,6 +95,10 @@ _SIGS = {
     "nn_solve_workspace_size": (_sz, [_i64, _i64, ctypes.c_int, _PP]),
     "nn_solve": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i64, _i64, ctypes.c_int, _PP,
                                 _p, _sz, ctypes.POINTER(nn_info), ctypes.POINTER(ctypes.c_double)]),
+    "nn_solve_factorized_workspace_size": (_sz, [_i64, _i64, ctypes.c_int, _PP]),
+    "nn_solve_factorized": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i64, _i64,
+                                           ctypes.c_int, _PP, _p, _sz, ctypes.POINTER(nn_info),
+                                           ctypes.POINTER(ctypes.c_double)]),
     "nn_batched_workspace_size": (_sz, [_i32, ctypes.c_int]),
     "nn_invert_batched": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
                                          _sz, _p]),
@@ -281,6 +285,37 @@ def solve(A, B, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0,
     d["rel_residual"] = rel.value
     if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
         raise NNError(st, "nn_solve")
+    return Xs, d
+
+
+def solve_factorized(A, B, x0="transpose", tol=1e-10, max_factors=60, fixed_factors=0,
+                     ctx: Context | None = None, check=True):
+    """Xsol with A Xsol = B by nn_solve_factorized (Corollary 6 applied to B).
+    Returns (Xsol, info); info["iters"] is the number of factors and
+    info["rms"] the relative residual ||B - A Xsol||_F / ||B||_F."""
+    torch = _torch()
+    n, nrhs = B.shape
+    dt = dtype_code(A)
+    prm = make_params(1, x0, tol, max_factors, fixed_factors)
+    Xs = torch.empty((n, nrhs), dtype=A.dtype, device=A.device)
+    ctx = ctx or default_context(A.device.index or 0)
+    need = nn_solve_factorized_workspace_size(n, nrhs, dt, ctypes.byref(prm))
+    if need == 0:
+        raise NNError(NN_ERR_ARG, "nn_solve_factorized_workspace_size")
+    hold, ws_ptr, ws_bytes = workspace(need, A.device)
+    info = nn_info()
+    rel = ctypes.c_double(0.0)
+    st = nn_solve_factorized(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.stride(0),
+                             ctypes.c_void_p(B.data_ptr()), B.stride(0),
+                             ctypes.c_void_p(Xs.data_ptr()), Xs.stride(0), n, nrhs, dt,
+                             ctypes.byref(prm), ctypes.c_void_p(ws_ptr), ws_bytes,
+                             ctypes.byref(info), ctypes.byref(rel))
+    del hold
+    d = info.as_dict()
+    d["status"] = st
+    d["rel_residual"] = rel.value
+    if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
+        raise NNError(st, "nn_solve_factorized")
     return Xs, d
 
 
