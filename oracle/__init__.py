@@ -13,6 +13,8 @@ via GPU acceleration", arXiv 2212.02406):
                  tiny integer matrices.
 * ``nn_fp64.nn_factorized_solve_ref`` — the factorised series of Corollary 6
                  applied to a right-hand side (A x = B without forming X).
+* ``nn_fp64.nn_cns_solve_ref`` — the Chebyshev-Neumann series: NN nests as
+                 the preconditioner of a Neumann series applied to B.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import or run anything in here.  The product path (the HIP
@@ -30,5 +32,5 @@ from .nn_fp64 import (  # noqa: F401
     OK, NOT_CONVERGED, STAGNATED, ERR_ARG, ERR_DIVERGED, ERR_NONFINITE,
     X0_TRANSPOSE, X0_SCALED_IDENTITY, X0_GIVEN,
     norm_1, norm_inf, initial_guess, residual, rms_of, nn_step, nn_ref,
-    nn_solve_ref, nn_factorized_solve_ref, nn_batched_ref,
+    nn_solve_ref, nn_factorized_solve_ref, nn_cns_solve_ref, nn_batched_ref,
 )

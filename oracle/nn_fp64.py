@@ -304,6 +304,82 @@ def nn_factorized_solve_ref(A, B, x0: int = X0_TRANSPOSE, tol: float = 1e-10,
         s += 1
 
 
+def nn_cns_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, nests: int = 1,
+                     precond_tol: float = 1e-2, max_nests: int = 100, tol: float = 1e-12,
+                     max_terms: int = 100, fixed_terms: int | None = None):
+    """Chebyshev-Neumann series solve, CNS (Sec. II-D, the CNS equation after
+    Corollary 2; d = 1 is the Newton-Neumann series): the NN iterate phi = X_m
+    is the preconditioner of a Neumann series applied to B,
+
+        x = sum_{k=0}^{T} (I - phi A)^k phi B,
+
+    the series of order (d+1)^m (T + 1) - 1 in the start's P = I - X_0 A (the
+    order printed in the paper is garbled; this is the reading that follows
+    from I - phi A = P^((d+1)^m)).  phi comes from nn_ref: ``nests`` > 0 fixed nests,
+    ``nests`` == 0 tolerance mode down to rms < precond_tol.  The series is
+    summed term by term as printed: t_0 = phi B, t_{k+1} = (I - phi A) t_k,
+    x_T = t_0 + ... + t_T.
+
+    Control on rel_T = ||B - A x_T||_F / ||B||_F, for T = 0, 1, ...: fixed
+    mode (fixed_terms given) stops at T == fixed_terms; tolerance mode uses the
+    rules of nn_factorized_solve_ref with max_terms.  A failed preconditioner
+    (status < 0) is returned as is.
+
+    Returns (x, info) with info = {"nests", "precond_rms", "terms",
+    "rel_residual", "status", "trace"}.
+    """
+    A = np.asarray(A)
+    B = np.asarray(B)
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B)
+    dt = np.complex128 if cplx else np.float64
+    A = A.astype(dt)
+    B = B.astype(dt)
+    if nests > 0:
+        phi, pinfo = nn_ref(A, d=d, x0=x0, fixed_iter=nests)
+    else:
+        phi, pinfo = nn_ref(A, d=d, x0=x0, tol=precond_tol, max_iter=max_nests)
+    info = {"nests": pinfo["iters"], "precond_rms": pinfo["rms"], "terms": 0,
+            "rel_residual": math.nan, "status": OK, "trace": []}
+    if pinfo["status"] < 0:
+        info["status"] = pinfo["status"]
+        return phi @ B, info
+    n = A.shape[0]
+    Q = np.eye(n, dtype=dt) - phi @ A
+    t = phi @ B
+    x = t.copy()
+    bnorm = float(np.linalg.norm(B))
+    x_prev, rel_prev = None, math.nan
+    T = 0
+    while True:
+        rel = float(np.linalg.norm(B - A @ x)) / bnorm if bnorm > 0 else 0.0
+        info["trace"].append(rel)
+        if fixed_terms is not None:
+            if T == fixed_terms:
+                info.update(terms=T, rel_residual=rel,
+                            status=OK if math.isfinite(rel) else ERR_NONFINITE)
+                return x, info
+        else:
+            if not math.isfinite(rel):
+                info.update(terms=T, rel_residual=rel, status=ERR_NONFINITE)
+                return x, info
+            if rel < tol:
+                info.update(terms=T, rel_residual=rel, status=OK)
+                return x, info
+            if T > 0 and rel >= 1.0 and rel > rel_prev:
+                info.update(terms=T, rel_residual=rel, status=ERR_DIVERGED)
+                return x, info
+            if T > 0 and rel_prev < 0.1 and rel >= rel_prev:
+                info.update(terms=T - 1, rel_residual=rel_prev, status=STAGNATED)
+                return x_prev, info
+            if T == max_terms:
+                info.update(terms=T, rel_residual=rel, status=NOT_CONVERGED)
+                return x, info
+        t = Q @ t
+        x_prev, rel_prev = x, rel
+        x = x + t
+        T += 1
+
+
 def nn_batched_ref(mats, d: int = 2, x0: int = X0_TRANSPOSE, fixed_iter: int = 4):
     """The batched form: each matrix of ``mats`` independently, fixed nests.
 
