@@ -1,7 +1,7 @@
 """Benchmark of the NN inversion on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--no-extras | --legs fp32,factorized,batched,mixed,serving]
+                    [--no-extras | --legs fp32,factorized,cns,batched,mixed,serving]
 
 A step is one whole inversion through the C ABI: start-iterate prologue, then
 nests of d + 1 GEMMs until rms = ||I - A X||_F / sqrt(N) < tol.  The headline
@@ -22,7 +22,9 @@ GEMM source), the oracle timed on the host on a bounded sample, and under
   serving  a Poisson request stream through the continuous-batching server,
            p50/p99 latency and inverses/s, against plain FP64 one by one;
   factorized  A X = B (64 right-hand sides) on the headline matrix with the
-           factorised series of Corollary 6, against nn_solve.
+           factorised series of Corollary 6, against nn_solve;
+  cns      the same system by the Chebyshev-Neumann series (plain and mixed
+           nests for the preconditioner), against nn_solve.
 """
 import argparse
 import json
@@ -51,7 +53,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp32,factorized,batched,mixed,serving",
+    ap.add_argument("--legs", default="fp32,factorized,cns,batched,mixed,serving",
                     help="comma list of extra workloads to run")
     ap.add_argument("--mixed-n", type=int, default=16384)
     ap.add_argument("--serve-pool", type=int, default=64)
@@ -281,6 +283,59 @@ def leg_factorized(nn, torch, workloads, np, A, n):
     return out
 
 
+def leg_cns(nn, torch, workloads, np, A, n):
+    """A X = B for the headline matrix and 64 right-hand sides by the
+    Chebyshev-Neumann series (NN nests for phi, then the series in I - phi A
+    applied to B, in refinement form) against nn_solve, all to FP64
+    accuracy: CNS to relative residual 1e-12; nn_solve with the inverse to
+    rms 1e-12.  Variants: plain FP64 nests (transpose start, phi to rms
+    1e-2); mixed BF16/FP32 nests (identity start, phi to rms 1e-2); and a
+    second right-hand-side batch against the kept phi (reuse)."""
+    B = torch.from_numpy(workloads.rng(9).standard_normal((n, 64))).cuda()
+    B2 = torch.from_numpy(workloads.rng(10).standard_normal((n, 64))).cuda()
+    out = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = fn()
+        torch.cuda.synchronize()
+        return X, info, time.perf_counter() - t0
+
+    runs = (("cns_plain", lambda: nn.solve_cns(A, B, x0="transpose", precond_tol=1e-2, tol=1e-12)),
+            ("cns_mixed", lambda: nn.solve_cns(A, B, x0="identity", precond_tol=1e-2,
+                                               prec="mixed", tol=1e-12)),
+            ("nn_solve", lambda: nn.solve(A, B, depth=2, x0="transpose", tol=1e-12)))
+    for label, fn in runs:
+        fn()
+        X, info, t = timed(fn)
+        rec = {"s": t, "solves_per_s": 1.0 / t, "status": info["status"],
+               "rel_residual": info["rel_residual"], "gemms": info["gemms"]}
+        if "precond" in info:
+            p = info["precond"]
+            rec.update(terms=info["iters"], nests=p["iters"], precond_rms=p["rms"],
+                       precond_phase_iters=p["phase_iters"], precond_gemms=p["gemms"],
+                       series_device_ms=info["device_ms"], precond_device_ms=p["device_ms"])
+            if label == "cns_mixed":
+                ws = info["ws"]
+                _, i2, t2 = timed(lambda: nn.solve_cns(A, B2, x0="identity", precond_tol=1e-2,
+                                                       prec="mixed", tol=1e-12, ws=ws,
+                                                       reuse_phi=True))
+                out["cns_reuse_phi"] = {"s": t2, "solves_per_s": 1.0 / t2,
+                                        "status": i2["status"], "terms": i2["iters"],
+                                        "rel_residual": i2["rel_residual"]}
+                log(f"cns leg cns_reuse_phi: {out['cns_reuse_phi']}")
+        else:
+            rec["nests"] = info["iters"]
+        out[label] = rec
+        log(f"cns leg {label}: {rec}")
+    for label in ("cns_plain", "cns_mixed"):
+        out[f"speedup_{label}_vs_nn_solve"] = out["nn_solve"]["s"] / out[label]["s"]
+    out["workload"] = (f"dense SPD N={n} FP64 cond 1e3 (the headline matrix), 64 right-hand "
+                       "sides N(0,1) seeds 9 and 10")
+    return out
+
+
 def leg_serving(nn, torch, workloads, np, pool_size, n_req):
     """Poisson request stream over a pool of FP32 SPD / complex64 HPD
     matrices, N log-uniform in [32, 4096], cond log-uniform in [10, 1e4],
@@ -445,6 +500,9 @@ def main():
         del A32, X32
     if "factorized" in legs:
         extra["factorized"] = leg_factorized(nn, torch, workloads, np, A, n)
+    if "cns" in legs:
+        extra["cns"] = leg_cns(nn, torch, workloads, np, A, n)
+        torch.cuda.empty_cache()
     if legs & {"batched", "mixed", "serving"}:
         del X
         torch.cuda.empty_cache()

@@ -190,6 +190,64 @@ nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const voi
                               nn_dtype dtype, const nn_params* params, void* ws,
                               size_t ws_bytes, nn_info* info, double* rel_residual);
 
+/* Parameters of nn_solve_cns. */
+typedef struct {
+  nn_params precond;   /* the NN preconditioner phi = X_m, as for nn_invert:
+                          precond.fixed_iter > 0 nests, or its tolerance mode
+                          on the rms of I - A phi (precond.tol, max_iter);
+                          prec NN_PREC_MIXED for NN_F64 only; NN_X0_GIVEN
+                          takes the start from the first n x n elements of
+                          the workspace */
+  double tol;          /* series tolerance mode: stop when the relative
+                          residual ||B - A Xsol||_F / ||B||_F < tol (>= 0) */
+  int32_t max_terms;   /* series tolerance mode: at most this many terms,
+                          1..NN_CNS_MAX_TERMS */
+  int32_t fixed_terms; /* >= 0: exactly this many terms (no host
+                          synchronisation in the series); -1: tolerance mode */
+  int32_t reuse_phi;   /* 1: the workspace already holds phi from an earlier
+                          call on the same A, n, dtype and precond; no nests are
+                          run and *precond_info is zeroed.  0: compute phi */
+  int32_t reserved;    /* must be 0 */
+} nn_cns_params;
+
+#define NN_CNS_MAX_TERMS 1000000
+
+/* Workspace bytes nn_solve_cns needs (0 on bad arguments). */
+size_t nn_solve_cns_workspace_size(int64_t n, int64_t nrhs, nn_dtype dtype,
+                                   const nn_cns_params* params);
+
+/* Solve A Xsol = B with the Chebyshev-Neumann series (CNS, Sec. II-D, the
+ * CNS equation after Corollary 2; depth 1 gives the Newton-Neumann series):
+ * m NN nests give the preconditioner phi = X_m, then T terms of the Neumann
+ * series in I - phi A are applied to B,
+ *     Xsol = sum_{k=0}^{T} (I - phi A)^k phi B,
+ * which is the plain Neumann series of order (d+1)^m (T+1) - 1 in the start's
+ * I - X_0 A.  The series is evaluated in its Horner form, one refinement step
+ * per term:  y_0 = phi B,  y_{k+1} = y_k + phi (B - A y_k)  (two n x n x nrhs
+ * products per term, the residual with its fused sum of squares; I - phi A is
+ * never formed, so the residual is always that of the returned iterate).
+ *   Workspace: the first n x n elements (leading dimension n) hold phi on
+ *     return and are read back with reuse_phi = 1 (many right-hand-side
+ *     batches against one A: the preconditioner is paid once).
+ *   Series control on rel_T = ||B - A y_T||_F / ||B||_F (0 when B = 0):
+ *     fixed_terms >= 0 stops at T = fixed_terms (one host synchronisation at
+ *     the end); tolerance mode uses nn_solve_factorized's rules with
+ *     max_terms (stagnation returns the previous iterate).
+ *   A preconditioner error (negative status of the nests) is returned as the
+ *     call's status, Xsol unspecified; a positive status of the nests
+ *     (NOT_CONVERGED, STAGNATED) is reported in precond_info and the series
+ *     still runs.
+ *   precond_info (optional): nn_invert's record of the nests.  info
+ *     (optional): iters = terms applied, rms = relative residual of the
+ *     returned Xsol (also *rel_residual if non-NULL), gemms = products of the
+ *     series, the trace holds rel_0, rel_1, ..., device_ms the series' time.
+ * B (n x nrhs, ldb) and Xsol (n x nrhs, ldx) are device arrays; Xsol must
+ * not alias A, B or the workspace.  Supported: F64, F32, C64, C128. */
+nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                       void* Xsol, int64_t ldx, int64_t n, int64_t nrhs, nn_dtype dtype,
+                       const nn_cns_params* params, void* ws, size_t ws_bytes,
+                       nn_info* precond_info, nn_info* info, double* rel_residual);
+
 /* Workspace bytes nn_invert_batched needs for `batch` matrices. */
 size_t nn_batched_workspace_size(int32_t batch, nn_dtype dtype);
 

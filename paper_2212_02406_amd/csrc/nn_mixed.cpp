@@ -13,7 +13,9 @@
 //      tolerance (rms^((d+1)^2) < tol: each exact nest raises the residual to
 //      the power d+1, Appendix 2), or until the rms stagnates in the asymptotic
 //      regime (sqrt(N) rms_{k-1} < 0.1 and rms_k >= rms_{k-1} / 2) — the FP32
-//      rounding floor.
+//      rounding floor.  A loose tolerance (tol >= 1e-4, far above that floor:
+//      a preconditioner) is met by the FP32 iterate itself: the phase then
+//      runs until the FP32 rms is below tol, and phase D only confirms it.
 //   D  FP64 residual and FP64 refinement nests until rms < tol.
 //
 // The transpose start squares the condition number (A X_0 = s A A^H); with
@@ -33,6 +35,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr double kUbf16 = 1.0 / 256.0;  // BF16 unit roundoff 2^-8
 constexpr double kTauB = 0.1;
+constexpr double kLooseTol = 1e-4;  // tolerances the FP32 iterate can meet
 
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -250,7 +253,9 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
     if (!isfinite(rms)) return finish(NN_ERR_NONFINITE, rms);
     if (rms >= 1.0 && rms > rms_prev) return finish(NN_ERR_DIVERGED, rms);
     if (iters >= max_iter) break;
-    if (pow(rms, (double)((r.d + 1) * (r.d + 1))) < prm->tol) break;        // two FP64 nests suffice
+    if (prm->tol >= kLooseTol ? rms < prm->tol                              // FP32 meets it
+                              : pow(rms, (double)((r.d + 1) * (r.d + 1))) < prm->tol)  // two FP64 nests
+      break;
     if (sqrt((double)n) * rms_prev < 0.1 && rms >= 0.5 * rms_prev) break;  // FP32 floor
     rms_prev = rms;
     float* U[2] = {w.U32[0], w.U32[1]};

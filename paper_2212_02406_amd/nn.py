@@ -33,6 +33,7 @@ NN_PREC_PLAIN, NN_PREC_MIXED = 0, 1
 NN_MAX_DEPTH = 8
 NN_TRACE_MAX = 128
 NN_FLAG_TIME_GEMMS = 1
+NN_CNS_MAX_TERMS = 1000000
 
 X0_NAMES = {"transpose": NN_X0_TRANSPOSE, "identity": NN_X0_SCALED_IDENTITY,
             "scaled_identity": NN_X0_SCALED_IDENTITY, "given": NN_X0_GIVEN}
@@ -56,6 +57,12 @@ class nn_info(ctypes.Structure):
                 "device_ms": self.device_ms, "gemm_ms": self.gemm_ms, "gemms": self.gemms,
                 "phase_iters": list(self.phase_iters),
                 "trace": [self.rms_trace[i] for i in range(self.n_trace)]}
+
+
+class nn_cns_params(ctypes.Structure):
+    _fields_ = [("precond", nn_params), ("tol", ctypes.c_double), ("max_terms", ctypes.c_int32),
+                ("fixed_terms", ctypes.c_int32), ("reuse_phi", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class nn_info_dev(ctypes.Structure):
@@ -99,6 +106,12 @@ _SIGS = {
     "nn_solve_factorized": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i64, _i64,
                                            ctypes.c_int, _PP, _p, _sz, ctypes.POINTER(nn_info),
                                            ctypes.POINTER(ctypes.c_double)]),
+    "nn_solve_cns_workspace_size": (_sz, [_i64, _i64, ctypes.c_int,
+                                          ctypes.POINTER(nn_cns_params)]),
+    "nn_solve_cns": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i64, _i64, ctypes.c_int,
+                                    ctypes.POINTER(nn_cns_params), _p, _sz,
+                                    ctypes.POINTER(nn_info), ctypes.POINTER(nn_info),
+                                    ctypes.POINTER(ctypes.c_double)]),
     "nn_batched_workspace_size": (_sz, [_i32, ctypes.c_int]),
     "nn_invert_batched": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
                                          _sz, _p]),
@@ -316,6 +329,62 @@ def solve_factorized(A, B, x0="transpose", tol=1e-10, max_factors=60, fixed_fact
     d["rel_residual"] = rel.value
     if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
         raise NNError(st, "nn_solve_factorized")
+    return Xs, d
+
+
+def make_cns_params(depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nests=100,
+                    prec="plain", tol=1e-12, max_terms=100, fixed_terms=None, reuse_phi=False):
+    c = nn_cns_params()
+    c.precond = make_params(depth, x0, precond_tol, max_nests, nests, prec)
+    c.tol = float(tol)
+    c.max_terms = int(max_terms)
+    c.fixed_terms = -1 if fixed_terms is None else int(fixed_terms)
+    c.reuse_phi = 1 if reuse_phi else 0
+    c.reserved = 0
+    return c
+
+
+def solve_cns(A, B, depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nests=100,
+              prec="plain", tol=1e-12, max_terms=100, fixed_terms=None, ws=None,
+              reuse_phi=False, ctx: Context | None = None, check=True):
+    """Xsol with A Xsol = B by nn_solve_cns: NN nests for phi (``nests`` > 0
+    fixed, else down to rms < precond_tol), then the Neumann series in
+    I - phi A applied to B (``fixed_terms`` terms, else down to the relative
+    residual ``tol``).  Returns (Xsol, info): info["iters"] = terms,
+    info["rms"] = info["rel_residual"] = ||B - A Xsol||_F / ||B||_F,
+    info["precond"] = the nests' record, info["ws"] = the workspace, whose
+    head holds phi: pass it back as ``ws`` with ``reuse_phi=True`` to solve
+    further right-hand sides against the same A without new nests."""
+    torch = _torch()
+    if B.dim() != 2 or B.stride(1) != 1 or A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A and B must be row-major matrices")
+    n, nrhs = B.shape
+    dt = dtype_code(A)
+    prm = make_cns_params(depth, x0, nests, precond_tol, max_nests, prec, tol, max_terms,
+                          fixed_terms, reuse_phi)
+    Xs = torch.empty((n, nrhs), dtype=A.dtype, device=A.device)
+    ctx = ctx or default_context(A.device.index or 0)
+    need = nn_solve_cns_workspace_size(n, nrhs, dt, ctypes.byref(prm))
+    if need == 0:
+        raise NNError(NN_ERR_ARG, "nn_solve_cns_workspace_size")
+    if ws is None:
+        if reuse_phi:
+            raise ValueError("reuse_phi needs the workspace of an earlier call")
+        ws = workspace(need, A.device)
+    _, ws_ptr, ws_bytes = ws
+    pinfo, info = nn_info(), nn_info()
+    rel = ctypes.c_double(0.0)
+    st = nn_solve_cns(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.stride(0),
+                      ctypes.c_void_p(B.data_ptr()), B.stride(0), ctypes.c_void_p(Xs.data_ptr()),
+                      Xs.stride(0), n, nrhs, dt, ctypes.byref(prm), ctypes.c_void_p(ws_ptr),
+                      ws_bytes, ctypes.byref(pinfo), ctypes.byref(info), ctypes.byref(rel))
+    d = info.as_dict()
+    d["status"] = st
+    d["rel_residual"] = rel.value
+    d["precond"] = pinfo.as_dict()
+    d["ws"] = ws
+    if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
+        raise NNError(st, "nn_solve_cns")
     return Xs, d
 
 

@@ -37,6 +37,8 @@ def test_struct_layout():
     assert ctypes.sizeof(nn.nn_request_info) == 64
     assert nn.nn_request_info.rms.offset == 32
     assert ctypes.sizeof(nn.nn_server_stats) == 24
+    assert ctypes.sizeof(nn.nn_cns_params) == 56
+    assert nn.nn_cns_params.tol.offset == 32 and nn.nn_cns_params.reuse_phi.offset == 48
 
 
 def test_server_argument_errors_before_device_work():
@@ -75,6 +77,36 @@ def test_argument_errors_before_launch():
     assert nn.nn_workspace_size(16, nn.NN_F64, ctypes.byref(bad)) == 0
     assert nn.nn_workspace_size(0, nn.NN_F64, ctypes.byref(p)) == 0
     assert nn.nn_workspace_size(16, 9, ctypes.byref(p)) == 0
+
+
+def test_cns_argument_errors_and_workspace():
+    nn = _nn()
+    fake = ctypes.c_void_p(0x1000)
+    pi, inf = nn.nn_info(), nn.nn_info()
+    ok = nn.make_cns_params()
+    assert nn.nn_solve_cns(None, fake, 4, fake, 1, fake, 1, 4, 1, nn.NN_F64, ctypes.byref(ok),
+                           fake, 1 << 20, ctypes.byref(pi), ctypes.byref(inf), None) == nn.NN_ERR_ARG
+    sz = lambda c, n=256, r=8, dt=nn.NN_F64: nn.nn_solve_cns_workspace_size(n, r, dt, ctypes.byref(c))
+    base = sz(ok)
+    # phi + nn_invert's workspace + two n x nrhs buffers at least
+    inv = nn.nn_workspace_size(256, nn.NN_F64, ctypes.byref(ok.precond))
+    assert base >= 256 * 256 * 8 + inv + 2 * 256 * 8 * 8
+    assert sz(nn.make_cns_params(depth=1)) < base
+    assert sz(nn.make_cns_params(fixed_terms=0)) == base
+    for bad in (nn.make_cns_params(depth=0), nn.make_cns_params(tol=-1.0),
+                nn.make_cns_params(max_terms=0), nn.make_cns_params(fixed_terms=-2),
+                nn.make_cns_params(max_terms=nn.NN_CNS_MAX_TERMS + 1)):
+        assert sz(bad) == 0
+    c = nn.make_cns_params()
+    c.reserved = 1
+    assert sz(c) == 0
+    c = nn.make_cns_params()
+    c.reuse_phi = 2
+    assert sz(c) == 0
+    # the mixed preconditioner exists for FP64 only
+    assert sz(nn.make_cns_params(prec="mixed", x0="identity")) > 0
+    assert sz(nn.make_cns_params(prec="mixed", x0="identity"), dt=nn.NN_F32) == 0
+    assert sz(ok, n=0) == 0 and sz(ok, r=0) == 0 and sz(ok, dt=7) == 0
 
 
 def test_workspace_sizes_grow_with_depth_and_n():

@@ -1,0 +1,213 @@
+"""Parity of nn_solve_cns (the Chebyshev-Neumann series of Sec. II-D: NN
+nests as the preconditioner phi, then the Neumann series in I - phi A
+applied to B) with the oracle.
+
+The oracle sums the series as printed (t_{k+1} = (I - phi A) t_k); the
+device evaluates its Horner form, one refinement step y + phi (B - A y) per
+term.  Both are the same polynomial in A applied to B, so:
+* fixed nests and terms: FP64 / complex128 relative Frobenius <= 1e-10
+  against the oracle, and the relative-residual trace term by term;
+* tolerance mode: both satisfy x - A^-1 B = -A^-1 r, so they agree within
+  kappa (rel + rel_oracle); single precision within the forward error of a
+  single-precision solve, 64 u32 kappa;
+* full size (N = 8192 FP64, 64 right-hand sides): the spectral closed form
+  sum_{k<=T} (1 - lam x_m(lam))^k x_m(lam) = (1 - (1 - lam^2/s)^(M (T+1))) / lam,
+  M = (d+1)^m, and in tolerance mode kappa rel against A^-1 B.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_02406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+from paper_2212_02406_amd import nn  # noqa: E402
+
+DEV = torch.device("cuda:0")
+U32 = 2.0 ** -24
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _relF(X, Y):
+    return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
+
+
+def _dev(a, ld=None):
+    a = np.ascontiguousarray(a)
+    if ld is None or ld == a.shape[1]:
+        return torch.from_numpy(a).to(DEV)
+    big = np.zeros((a.shape[0], ld), dtype=a.dtype)
+    big[:, :a.shape[1]] = a
+    return torch.from_numpy(big).to(DEV)[:, :a.shape[1]]
+
+
+def _case(n, nrhs, cond, seed, dtype):
+    cplx = np.dtype(dtype).kind == "c"
+    A = W.dense_spd(n, 1.0, cond, seed, complex_=cplx, dtype=dtype)
+    g = W.rng(seed + 1)
+    B = g.standard_normal((n, nrhs)) + (1j * g.standard_normal((n, nrhs)) if cplx else 0.0)
+    return A, B.astype(dtype)
+
+
+@pytest.mark.parametrize("n,nrhs,ldb", [(1, 1, 1), (33, 7, 9), (100, 1, 1), (257, 33, 40),
+                                        (520, 64, 64)])
+@pytest.mark.parametrize("x0,d", [("transpose", 2), ("identity", 2), ("transpose", 1),
+                                  ("identity", 3)])
+def test_fixed_nests_and_terms_fp64_vs_oracle(n, nrhs, ldb, x0, d):
+    _say(f"cns fixed n={n} nrhs={nrhs} ldb={ldb} x0={x0} d={d}")
+    A, B = _case(n, nrhs, 50.0, 600 + n, np.float64)
+    x0c = oracle.X0_TRANSPOSE if x0 == "transpose" else oracle.X0_SCALED_IDENTITY
+    for m, T in ((1, 0), (2, 1), (3, 4)):
+        xo, io = oracle.nn_cns_solve_ref(A, B, d=d, x0=x0c, nests=m, fixed_terms=T)
+        X, info = nn.solve_cns(_dev(A), _dev(B, ldb), depth=d, x0=x0, nests=m, fixed_terms=T)
+        torch.cuda.synchronize()
+        assert info["status"] == nn.NN_OK and info["iters"] == T
+        assert info["precond"]["iters"] == m and info["gemms"] == 2 * T + 2
+        assert _relF(X.cpu().numpy(), xo) < 1e-10, (m, T)
+        assert len(info["trace"]) == T + 1
+        for a, b in zip(info["trace"], io["trace"]):
+            assert abs(a - b) <= 1e-9 * b + 1e-14
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.complex128, np.float32, np.complex64])
+def test_tolerance_mode_vs_oracle(dtype):
+    _say(f"cns tol {np.dtype(dtype).name}")
+    single = np.dtype(dtype) in (np.dtype(np.float32), np.dtype(np.complex64))
+    n, nrhs = 300, 5
+    cond = 10.0 if single else 100.0
+    A, B = _case(n, nrhs, cond, 700, dtype)
+    tol = 1e-4 if single else 1e-12
+    ref_dt = np.complex128 if np.dtype(dtype).kind == "c" else np.float64
+    xo, io = oracle.nn_cns_solve_ref(A.astype(ref_dt), B.astype(ref_dt), nests=0,
+                                     precond_tol=1e-2, tol=max(tol, 1e-11))
+    X, info = nn.solve_cns(_dev(A), _dev(B), nests=0, precond_tol=1e-2, tol=tol)
+    torch.cuda.synchronize()
+    assert io["status"] == oracle.OK and info["status"] == nn.NN_OK, info
+    assert info["precond"]["status"] == nn.NN_OK and info["precond"]["rms"] < 1e-2
+    assert abs(info["precond"]["iters"] - io["nests"]) <= 1
+    assert info["rms"] < tol and info["rel_residual"] == info["rms"]
+    x = X.cpu().numpy().astype(ref_dt)
+    if single:
+        assert _relF(x, xo) < 64 * U32 * cond + cond * 2 * tol
+    else:
+        assert _relF(x, xo) <= cond * (info["rms"] + io["rel_residual"]) * 1.01
+    # the returned residual is the true one, recomputed here in FP64
+    Ad, Bd = A.astype(ref_dt), B.astype(ref_dt)
+    true = np.linalg.norm(Bd - Ad @ x) / np.linalg.norm(Bd)
+    slack = 2 * n * U32 * np.linalg.norm(Ad) * np.linalg.norm(x) / np.linalg.norm(Bd) if single \
+        else 1e-14
+    assert abs(true - info["rms"]) <= 1e-6 * true + slack
+
+
+def test_refinement_form_beats_printed_series_floor():
+    """The Horner form recomputes B - A y from A every term, so at tol 0 it
+    stagnates at the rounding level of one product (well below the printed
+    series' floor, which carries the rounding of a formed I - phi A)."""
+    _say("cns floor")
+    A, B = _case(200, 3, 300.0, 710, np.float64)
+    X, info = nn.solve_cns(_dev(A), _dev(B), nests=0, tol=0.0)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_STAGNATED and info["rms"] < 1e-14, info["rms"]
+    _, io = oracle.nn_cns_solve_ref(A, B, nests=0, tol=0.0)
+    assert io["status"] == oracle.STAGNATED and info["rms"] <= io["rel_residual"]
+    assert _relF(X.cpu().numpy(), np.linalg.solve(A, B)) < 300.0 * 1e-14 * 4
+
+
+def test_reuse_phi_for_new_right_hand_sides():
+    _say("cns reuse phi")
+    n = 256
+    A, B1 = _case(n, 8, 100.0, 720, np.float64)
+    B2 = W.rng(722).standard_normal((n, 3))
+    At = _dev(A)
+    X1, i1 = nn.solve_cns(At, _dev(B1), nests=0, tol=1e-12)
+    ws = i1["ws"]
+    X2r, i2 = nn.solve_cns(At, _dev(B2), nests=0, tol=1e-12, ws=ws, reuse_phi=True)
+    torch.cuda.synchronize()
+    assert i2["precond"]["iters"] == 0 and i2["precond"]["gemms"] == 0
+    assert i2["status"] == nn.NN_OK
+    # a fresh call computes the same phi bit for bit, hence the same series
+    X2f, i2f = nn.solve_cns(At, _dev(B2), nests=0, tol=1e-12)
+    torch.cuda.synchronize()
+    assert torch.equal(X2r, X2f) and i2["iters"] == i2f["iters"]
+    xo, _ = oracle.nn_cns_solve_ref(A, B2, nests=i1["precond"]["iters"], fixed_terms=i2["iters"])
+    assert _relF(X2r.cpu().numpy(), xo) < 1e-10
+
+
+def test_mixed_preconditioner_fp64_series():
+    """BF16/FP32 nests for phi (mixed schedule, loose tolerance), FP64
+    series: the classic mixed-precision refinement, to an FP64 solution."""
+    _say("cns mixed preconditioner")
+    n = 512
+    A = W.dense_spd(n, 1.0, 1e3, 730, log_spectrum=True)
+    B = W.rng(731).standard_normal((n, 16))
+    X, info = nn.solve_cns(_dev(A), _dev(B), x0="identity", nests=0, precond_tol=1e-2,
+                           prec="mixed", tol=1e-12)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK and info["rms"] < 1e-12, info
+    p = info["precond"]
+    assert p["status"] == nn.NN_OK and p["rms"] < 1e-2 and p["phase_iters"][2] == 0
+    x = X.cpu().numpy()
+    assert _relF(x, np.linalg.solve(A, B)) <= 1e3 * info["rms"] * 1.01 + 1e-13
+    assert abs(np.linalg.norm(B - A @ x) / np.linalg.norm(B) - info["rms"]) <= 1e-6 * info["rms"] + 1e-15
+
+
+def test_statuses_and_arguments():
+    _say("cns statuses")
+    n = 40
+    A, B = _case(n, 2, 10.0, 740, np.float64)
+    X, info = nn.solve_cns(_dev(-np.eye(n)), _dev(B), x0="identity", nests=2, check=False)
+    _, io = oracle.nn_cns_solve_ref(-np.eye(n), B, x0=oracle.X0_SCALED_IDENTITY, nests=2)
+    assert info["status"] == nn.NN_ERR_DIVERGED and io["status"] == oracle.ERR_DIVERGED
+    assert info["precond"]["status"] == nn.NN_ERR_DIVERGED
+    An = A.copy()
+    An[1, 2] = np.nan
+    X, info = nn.solve_cns(_dev(An), _dev(B), nests=2, check=False)
+    assert info["status"] == nn.NN_ERR_NONFINITE
+    X, info = nn.solve_cns(_dev(A), _dev(B), nests=1, tol=1e-15, max_terms=2)
+    _, io = oracle.nn_cns_solve_ref(A, B, nests=1, tol=1e-15, max_terms=2)
+    assert info["status"] == nn.NN_NOT_CONVERGED == io["status"] and info["iters"] == 2
+    X, info = nn.solve_cns(_dev(A), _dev(B), nests=0, tol=0.0)
+    assert info["status"] == nn.NN_STAGNATED and info["rms"] < 1e-13
+    # a zero right-hand side: relative residual 0 after phi B
+    X, info = nn.solve_cns(_dev(A), _dev(np.zeros((n, 2))), nests=2, tol=1e-12)
+    assert info["status"] == nn.NN_OK and info["iters"] == 0 and float(X.abs().max()) == 0.0
+    with pytest.raises(nn.NNError):  # the mixed preconditioner is FP64 only
+        nn.solve_cns(_dev(A.astype(np.float32)), _dev(B.astype(np.float32)), prec="mixed",
+                     x0="identity")
+    with pytest.raises(ValueError):
+        nn.solve_cns(_dev(A), _dev(B), reuse_phi=True)
+
+
+def test_full_size_n8192_closed_form():
+    """The headline matrix (N = 8192 FP64, cond 1e3), 64 right-hand sides."""
+    n, nrhs, d = 8192, 64, 2
+    _say("cns n=8192 nrhs=64")
+    A, lam, Q = W.dense_spd(n, 1.0, 1e3, 2, log_spectrum=True, device="cuda",
+                            return_factors=True)
+    B = W.rng(9).standard_normal((n, nrhs))
+    At, Bt = _dev(A), _dev(B)
+    m, T = 6, 5
+    X, info = nn.solve_cns(At, Bt, depth=d, x0="transpose", nests=m, fixed_terms=T)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK and info["iters"] == T
+    s = np.abs(A).sum(axis=0).max() * np.abs(A).sum(axis=1).max()
+    M = (d + 1) ** m
+    f = (1.0 - (1.0 - lam ** 2 / s) ** (M * (T + 1))) / lam
+    ref = Q @ (f[:, None] * (Q.T @ B))
+    assert _relF(X.cpu().numpy(), ref) < 1e-10
+    X, info = nn.solve_cns(At, Bt, depth=d, x0="transpose", nests=0, precond_tol=1e-2,
+                           tol=1e-10)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK and info["rms"] < 1e-10
+    exact = Q @ ((Q.T @ B) / lam[:, None])
+    assert _relF(X.cpu().numpy(), exact) <= 1e3 * info["rms"] * 1.01

@@ -75,3 +75,24 @@ def test_mixed_status_nonpositive_trace():
     A = torch.from_numpy(-W.dense_spd(64, 1.0, 10.0, 3)).to(DEV)
     _, info = nn.invert(A, prec="mixed", x0="identity", check=False)
     assert info["status"] == nn.NN_ERR_DIVERGED
+
+
+@pytest.mark.parametrize("n,tol", [(512, 1e-3), (1000, 1e-2)])
+def test_mixed_loose_tolerance_ends_in_fp32(n, tol):
+    """A tolerance far above the FP32 floor (a preconditioner's) is met by the
+    FP32 iterate: no FP64 nest, the FP64 check of the returned X below tol."""
+    _say(f"mixed loose n={n} tol={tol:g}")
+    A = W.dense_spd(n, 1.0, 1e3, 60 + n, log_spectrum=True)
+    X, info = nn.invert(torch.from_numpy(A).to(DEV), depth=2, x0="identity", tol=tol,
+                        max_iter=200, prec="mixed")
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK, info
+    pb, pf, pd = info["phase_iters"]
+    assert pd == 0 and pb + pf == info["iters"], info["phase_iters"]
+    Xh = X.cpu().numpy()
+    rms = np.linalg.norm(np.eye(n) - A @ Xh) / np.sqrt(n)
+    assert rms < tol and abs(rms - info["rms"]) <= 1e-9 * rms + 1e-13
+    # the iterate is the oracle's NN trajectory to within the single-precision
+    # perturbation: the oracle's rms after the same number of nests is close
+    _, io = oracle.nn_ref(A, d=2, x0=oracle.X0_SCALED_IDENTITY, fixed_iter=info["iters"])
+    assert rms <= 4.0 * io["rms"] + 1e-6
