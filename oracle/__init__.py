@@ -30,7 +30,8 @@ the order of convergence).  Nothing in this package is "parity unpinned".
 
 from .nn_fp64 import (  # noqa: F401
     OK, NOT_CONVERGED, STAGNATED, ERR_ARG, ERR_DIVERGED, ERR_NONFINITE,
-    X0_TRANSPOSE, X0_SCALED_IDENTITY, X0_GIVEN,
+    X0_TRANSPOSE, X0_SCALED_IDENTITY, X0_GIVEN, X0_TRANSPOSE_FROB, X0_POWER_IDENTITY,
+    X0_POWER_TRANSPOSE, X0_JACOBI, splitmix64, power_vector, theta2,
     norm_1, norm_inf, initial_guess, residual, rms_of, nn_step, nn_ref,
     nn_solve_ref, nn_factorized_solve_ref, nn_cns_solve_ref, nn_batched_ref,
 )

@@ -28,6 +28,13 @@ design notes of the repository):
   start that Sec. II-C and Corollary 5 refer to; it is the normal-equation
   route of Corollary 3 (A X_0 is Hermitian PSD) and works for any
   nonsingular A.  ``X0_GIVEN`` takes a caller-supplied X_0 (restart).
+* Other normalisations (Sec. II-A and the linear-system form of Sec. II-D):
+  ``X0_TRANSPOSE_FROB`` X_0 = A^H / ||A||_F^2 (Theta = 1/Tr(A^H A));
+  ``X0_POWER_IDENTITY`` / ``X0_POWER_TRANSPOSE`` scale I or A^H by the
+  power-iteration estimate Theta_2(k), printed with squared norms (which
+  would tend to 1/lambda^2) and read here with plain norms (1/lambda_max);
+  its random vector comes from SplitMix64 so that the device draws the same
+  one; ``X0_JACOBI`` X_0 = diag(A)^-1, the diagonal preconditioner.
 * Accuracy measure.  rms = ||I - A X||_F / sqrt(N) ("root mean Frobenius
   norm error", Sec. II).  The paper iterates a fixed number of nests; a
   tolerance stop on this rms, tested before each update, is our addition.
@@ -52,6 +59,58 @@ ERR_NONFINITE = -3
 X0_TRANSPOSE = 0
 X0_SCALED_IDENTITY = 1
 X0_GIVEN = 2
+X0_TRANSPOSE_FROB = 3
+X0_POWER_IDENTITY = 4
+X0_POWER_TRANSPOSE = 5
+X0_JACOBI = 6
+
+# Odd constant of SplitMix64 (Steele, Lea and Flood, "Fast splittable
+# pseudorandom number generators", OOPSLA 2014): the state advances by it.
+_SM64_GAMMA = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(state: int) -> int:
+    """The SplitMix64 output function applied to a 64-bit state (the state
+    after its increment): two xor-shift-multiply rounds and a final
+    xor-shift, all modulo 2^64."""
+    z = state & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def power_vector(n: int) -> np.ndarray:
+    """The random vector v of the Theta_2 estimate (Sec. II-A), drawn from a
+    counter-based generator so that any implementation reproduces it: entry i
+    is the (i+1)-th SplitMix64 output from seed 0, its top 53 bits scaled to
+    u in [0, 1), and v_i = 2 u - 1."""
+    out = np.empty(n)
+    for i in range(n):
+        z = splitmix64(((i + 1) * _SM64_GAMMA) & _M64)
+        out[i] = 2.0 * ((z >> 11) * 2.0 ** -53) - 1.0
+    return out
+
+
+def theta2(apply_w, v: np.ndarray, k: int) -> float:
+    """Theta_2(k) = k ||W^k v||_2 / ((k + 1) ||W^(k+1) v||_2)  (Sec. II-A,
+    the normalisation equation; the norms are read unsquared, so that
+    Theta_2 estimates 1 / lambda_max of W, the scale the normalisation
+    needs).  W is given as a function w -> W w.  The powers are formed one
+    product at a time; between products the vector is rescaled by a power of
+    two (exact in binary floating point, and the ratio is unchanged) so that
+    W^k v cannot overflow."""
+    w = np.asarray(v, dtype=np.complex128 if np.iscomplexobj(v) else np.float64)
+    for _ in range(k):
+        w = apply_w(w)
+        m = float(np.max(np.abs(w)))
+        if m > 0.0 and math.isfinite(m):
+            w = w * 2.0 ** (-math.frexp(m)[1])
+    num = float(np.linalg.norm(w))
+    den = float(np.linalg.norm(apply_w(w)))
+    if not (math.isfinite(num) and math.isfinite(den)):
+        return math.nan
+    return k * num / ((k + 1) * den) if den > 0.0 else math.inf
 
 
 def norm_1(A: np.ndarray) -> float:
@@ -64,7 +123,8 @@ def norm_inf(A: np.ndarray) -> float:
     return float(np.max(np.sum(np.abs(A), axis=1)))
 
 
-def initial_guess(A: np.ndarray, x0: int, X_init: np.ndarray | None = None):
+def initial_guess(A: np.ndarray, x0: int, X_init: np.ndarray | None = None,
+                  power_k: int = 8):
     """Return (den, X_0), where X_0 = X_init for GIVEN, else (1/den) * M.
 
     * TRANSPOSE: den = ||A||_1 ||A||_inf, M = A^H.  Since
@@ -74,8 +134,43 @@ def initial_guess(A: np.ndarray, x0: int, X_init: np.ndarray | None = None):
     * SCALED_IDENTITY: den = Re Tr(A), M = I (Sec. II-A, trace
       normalisation Theta_1, with phi^(0) = I of Sec. II-D).
     * GIVEN: den = nan, X_0 = X_init.
+    * TRANSPOSE_FROB: den = ||A||_F^2 = Tr(A^H A), M = A^H: the Theta of the
+      normal-equation solve (Sec. II-D, linear systems), 1/Tr(A^H A).
+    * POWER_IDENTITY: den = 1 / Theta_2(power_k) of W = A, M = I.
+    * POWER_TRANSPOSE: den = 1 / Theta_2(power_k) of W = A A^H, M = A^H
+      (A X_0 = Theta_2 A A^H, the matrix whose top eigenvalue is estimated).
+    * JACOBI: X_0 = D^-1, D = diag(A) (the diagonal preconditioner of the
+      CNS discussion, Sec. II-D); den = min_i |a_ii| only flags a zero or
+      non-finite diagonal.  ||I - A D^-1||_2 < 1 is the caller's condition
+      (diagonally dominant A); for diagonal A, X_0 = A^-1 exactly.
     """
     n = A.shape[0]
+    if x0 == X0_TRANSPOSE_FROB:
+        den = float(np.sum(np.abs(A) ** 2))
+        s = 1.0 / den if den > 0.0 and math.isfinite(den) else math.nan
+        return den, s * A.conj().T
+    if x0 in (X0_POWER_IDENTITY, X0_POWER_TRANSPOSE):
+        if power_k < 1:
+            raise ValueError("power_k must be >= 1")
+        v = power_vector(n)
+        if x0 == X0_POWER_IDENTITY:
+            th = theta2(lambda w: A @ w, v, power_k)
+            M = np.eye(n, dtype=A.dtype)
+        else:
+            AH = A.conj().T
+            th = theta2(lambda w: A @ (AH @ w), v, power_k)
+            M = AH
+        den = 1.0 / th if th > 0.0 else math.nan
+        if not math.isfinite(th):
+            den = math.nan if math.isnan(th) else 0.0
+        s = 1.0 / den if math.isfinite(den) and den > 0.0 else math.nan
+        return den, s * M
+    if x0 == X0_JACOBI:
+        dg = np.diag(A)
+        den = float(np.min(np.abs(dg))) if np.all(np.isfinite(dg)) else math.nan
+        if not (math.isfinite(den) and den > 0.0):
+            return den, np.full(A.shape, math.nan, dtype=A.dtype)
+        return den, np.diag(1.0 / dg).astype(A.dtype)
     if x0 == X0_TRANSPOSE:
         den = norm_1(A) * norm_inf(A)
         s = 1.0 / den if den > 0.0 and math.isfinite(den) else math.nan
@@ -123,7 +218,7 @@ def nn_step(X: np.ndarray, R: np.ndarray, d: int) -> np.ndarray:
 
 def nn_ref(A, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
            max_iter: int = 100, fixed_iter: int | None = None,
-           X_init=None, trace_max: int = 1 << 20):
+           X_init=None, trace_max: int = 1 << 20, power_k: int = 8):
     """Run the NN iteration on A; return (X, info).
 
     info = {"iters", "rms", "status", "trace", "den"}.  ``iters`` is the
@@ -157,7 +252,7 @@ def nn_ref(A, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
     if A.dtype not in (np.float64, np.complex128):
         A = A.astype(np.complex128 if np.iscomplexobj(A) else np.float64)
     n = A.shape[0]
-    den, X = initial_guess(A, x0, X_init)
+    den, X = initial_guess(A, x0, X_init, power_k)
     info = {"iters": 0, "rms": math.nan, "status": OK, "trace": [], "den": den}
     if x0 != X0_GIVEN:
         if not math.isfinite(den):
@@ -201,14 +296,15 @@ def nn_ref(A, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
 
 
 def nn_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
-                 max_iter: int = 100, fixed_iter: int | None = None):
+                 max_iter: int = 100, fixed_iter: int | None = None, power_k: int = 8):
     """Solve A x = B (Corollary 3): x = X B with X the NN inverse of A.
 
     With X0_TRANSPOSE this is the normal-equation route of Corollary 3
     (A X_0 is Hermitian PSD for any nonsingular A).  Returns (x, info);
     info also gets "rel_residual" = ||B - A x||_F / ||B||_F.
     """
-    X, info = nn_ref(A, d=d, x0=x0, tol=tol, max_iter=max_iter, fixed_iter=fixed_iter)
+    X, info = nn_ref(A, d=d, x0=x0, tol=tol, max_iter=max_iter, fixed_iter=fixed_iter,
+                     power_k=power_k)
     x = X @ np.asarray(B, dtype=X.dtype)
     bnorm = float(np.linalg.norm(B))
     info["rel_residual"] = float(np.linalg.norm(B - A @ x)) / bnorm if bnorm > 0 else 0.0
@@ -216,7 +312,8 @@ def nn_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, tol: float = 1e-12,
 
 
 def nn_factorized_solve_ref(A, B, x0: int = X0_TRANSPOSE, tol: float = 1e-10,
-                            max_factors: int = 60, fixed_factors: int | None = None):
+                            max_factors: int = 60, fixed_factors: int | None = None,
+                            power_k: int = 8):
     """Solve A x = B with the factorised Neumann series applied to B, without
     forming the inverse (Corollary 6 and the linear-solve form after it):
 
@@ -259,7 +356,7 @@ def nn_factorized_solve_ref(A, B, x0: int = X0_TRANSPOSE, tol: float = 1e-10,
     A = A.astype(dt)
     B = B.astype(dt)
     n = A.shape[0]
-    den, phi = initial_guess(A, x0)
+    den, phi = initial_guess(A, x0, power_k=power_k)
     info = {"factors": 0, "rel_residual": math.nan, "status": OK, "trace": [], "den": den}
     if not math.isfinite(den):
         info["status"] = ERR_NONFINITE
@@ -306,7 +403,8 @@ def nn_factorized_solve_ref(A, B, x0: int = X0_TRANSPOSE, tol: float = 1e-10,
 
 def nn_cns_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, nests: int = 1,
                      precond_tol: float = 1e-2, max_nests: int = 100, tol: float = 1e-12,
-                     max_terms: int = 100, fixed_terms: int | None = None):
+                     max_terms: int = 100, fixed_terms: int | None = None,
+                     power_k: int = 8):
     """Chebyshev-Neumann series solve, CNS (Sec. II-D, the CNS equation after
     Corollary 2; d = 1 is the Newton-Neumann series): the NN iterate phi = X_m
     is the preconditioner of a Neumann series applied to B,
@@ -335,9 +433,10 @@ def nn_cns_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, nests: int = 1,
     A = A.astype(dt)
     B = B.astype(dt)
     if nests > 0:
-        phi, pinfo = nn_ref(A, d=d, x0=x0, fixed_iter=nests)
+        phi, pinfo = nn_ref(A, d=d, x0=x0, fixed_iter=nests, power_k=power_k)
     else:
-        phi, pinfo = nn_ref(A, d=d, x0=x0, tol=precond_tol, max_iter=max_nests)
+        phi, pinfo = nn_ref(A, d=d, x0=x0, tol=precond_tol, max_iter=max_nests,
+                            power_k=power_k)
     info = {"nests": pinfo["iters"], "precond_rms": pinfo["rms"], "terms": 0,
             "rel_residual": math.nan, "status": OK, "trace": []}
     if pinfo["status"] < 0:
