@@ -69,7 +69,21 @@ typedef enum {
      (Sec. II-A, Sec. II-D).  Hermitian positive definite A only. */
   NN_X0_SCALED_IDENTITY = 1,
   /* X holds the start on entry (restart from a saved iterate). */
-  NN_X0_GIVEN = 2
+  NN_X0_GIVEN = 2,
+  /* X_0 = A^H / ||A||_F^2: Theta = 1 / Tr(A^H A) of the normal-equation
+     solve (Sec. II-D, linear systems); any nonsingular A. */
+  NN_X0_TRANSPOSE_FROB = 3,
+  /* X_0 = Theta_2(k) I, Theta_2(k) = k ||A^k v|| / ((k+1) ||A^(k+1) v||)
+     (Sec. II-A; k = power_k): a power-iteration estimate of 1/lambda_max
+     with a k/(k+1) margin; Hermitian PD A.  v is the SplitMix64 vector
+     described at nn_params.power_k. */
+  NN_X0_POWER_IDENTITY = 4,
+  /* X_0 = Theta_2(k) A^H with W = A A^H in the estimate; any nonsingular A. */
+  NN_X0_POWER_TRANSPOSE = 5,
+  /* X_0 = diag(A)^-1, the diagonal preconditioner of the CNS discussion
+     (Sec. II-D); requires ||I - A diag(A)^-1||_2 < 1 (diagonally dominant
+     A), exact for diagonal A.  A zero diagonal entry gives DIVERGED. */
+  NN_X0_JACOBI = 6
 } nn_x0;
 
 typedef enum {
@@ -94,7 +108,15 @@ typedef struct {
                          max_iter ignored; 0: tolerance mode */
   int32_t prec;       /* nn_prec */
   int32_t flags;      /* 0 or NN_FLAG_TIME_GEMMS; other bits must be 0 */
+  int32_t power_k;    /* NN_X0_POWER_*: power steps k, 1..NN_POWER_MAX_K (the
+                         start then costs k + 1 matrix-vector products with A,
+                         twice that for POWER_TRANSPOSE); v_i = 2 u_i - 1 with
+                         u_i the top 53 bits / 2^53 of the (i+1)-th SplitMix64
+                         output from seed 0.  Ignored for other starts. */
+  int32_t reserved;   /* ignored; set to 0 */
 } nn_params;
+
+#define NN_POWER_MAX_K 64
 
 typedef struct {
   int32_t iters;      /* nests applied to X_0 to obtain the returned X */

@@ -51,6 +51,7 @@ struct PlainWs {
   void* u1 = nullptr;
   double* part = nullptr;     // per-tile partials of the residual GEMM
   double* denpart = nullptr;  // row sums / column partial sums for the norms
+  double* pw = nullptr;       // start-iterate scratch (power steps)
   double* scal = nullptr;     // [0] den
   double* stats = nullptr;    // rms per nest
   size_t bytes = 0;
@@ -68,6 +69,7 @@ PlainWs carve_plain(void* base, int64_t n, nn_dtype dt, int depth) {
   if (depth >= 3) w.u1 = c.take(mat);
   w.part = static_cast<double*>(c.take(sizeof(double) * (size_t)std::max(plan.num_tiles(), 1)));
   w.denpart = static_cast<double*>(c.take(sizeof(double) * den_partials_elems(n)));
+  w.pw = static_cast<double*>(c.take(sizeof(double) * start_scratch_doubles(n)));
   w.scal = static_cast<double*>(c.take(sizeof(double) * 8));
   w.stats = static_cast<double*>(c.take(sizeof(double) * kStatSlots));
   w.bytes = c.off;
@@ -79,7 +81,10 @@ bool valid_dtype(int d) { return d >= NN_F64 && d <= NN_C128; }
 nn_status check_params(const nn_params* p) {
   if (!p) return NN_ERR_ARG;
   if (p->depth < 1 || p->depth > NN_MAX_DEPTH) return NN_ERR_ARG;
-  if (p->x0 < NN_X0_TRANSPOSE || p->x0 > NN_X0_GIVEN) return NN_ERR_ARG;
+  if (p->x0 < NN_X0_TRANSPOSE || p->x0 > NN_X0_JACOBI) return NN_ERR_ARG;
+  if ((p->x0 == NN_X0_POWER_IDENTITY || p->x0 == NN_X0_POWER_TRANSPOSE) &&
+      (p->power_k < 1 || p->power_k > NN_POWER_MAX_K))
+    return NN_ERR_ARG;
   if (p->fixed_iter < 0) return NN_ERR_ARG;
   if (p->fixed_iter == 0) {
     if (!(p->tol >= 0.0) || p->max_iter < 1) return NN_ERR_ARG;
@@ -194,13 +199,8 @@ nn_status run_plain(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ld
   HIP_TRY(hipEventRecord(ctx->ev_start, s));
   // Start iterate X_0 in the caller's X.
   if (prm->x0 != NN_X0_GIVEN) {
-    if (prm->x0 == NN_X0_TRANSPOSE) {
-      HIP_TRY(launch_den_transpose(dt, A, lda, n, w.denpart, w.scal, s));
-      HIP_TRY(launch_x0_transpose(dt, A, lda, X, ldx, n, w.scal, s));
-    } else {
-      HIP_TRY(launch_den_trace(dt, A, lda, n, w.scal, s));
-      HIP_TRY(launch_x0_identity(dt, X, ldx, n, w.scal, s));
-    }
+    HIP_TRY(launch_start(dt, prm->x0, prm->power_k, A, lda, X, ldx, n, w.denpart, w.pw, w.scal,
+                         s));
     HIP_TRY(hipMemcpyAsync(ctx->host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const double den = ctx->host[0];

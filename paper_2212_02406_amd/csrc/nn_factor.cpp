@@ -39,6 +39,7 @@ struct FactorWs {
   void* r = nullptr;                // residual B - A y
   double* part = nullptr;
   double* denpart = nullptr;
+  double* pw = nullptr;     // start-iterate scratch
   double* scal = nullptr;   // [0] den, [1] ||B||_F
   double* stats = nullptr;  // ||B - A y_s||_F per s
   size_t bytes = 0;
@@ -64,6 +65,7 @@ FactorWs carve(void* base, int64_t n, int64_t nrhs, nn_dtype dt) {
   const int tiles = std::max({plan_gemm(el, n, cm * nrhs).num_tiles(), kSumsqParts, 1});
   w.part = static_cast<double*>(take(sizeof(double) * (size_t)tiles));
   w.denpart = static_cast<double*>(take(sizeof(double) * den_partials_elems(n)));
+  w.pw = static_cast<double*>(take(sizeof(double) * start_scratch_doubles(n)));
   w.scal = static_cast<double*>(take(sizeof(double) * 8));
   w.stats = static_cast<double*>(take(sizeof(double) * kStats));
   w.bytes = off;
@@ -72,9 +74,11 @@ FactorWs carve(void* base, int64_t n, int64_t nrhs, nn_dtype dt) {
 
 nn_status check(const nn_params* p) {
   if (!p) return NN_ERR_ARG;
-  if (p->x0 != NN_X0_TRANSPOSE && p->x0 != NN_X0_SCALED_IDENTITY) {
-    return p->x0 == NN_X0_GIVEN ? NN_ERR_UNSUPPORTED : NN_ERR_ARG;
-  }
+  if (p->x0 < NN_X0_TRANSPOSE || p->x0 > NN_X0_JACOBI) return NN_ERR_ARG;
+  if (p->x0 == NN_X0_GIVEN) return NN_ERR_UNSUPPORTED;
+  if ((p->x0 == NN_X0_POWER_IDENTITY || p->x0 == NN_X0_POWER_TRANSPOSE) &&
+      (p->power_k < 1 || p->power_k > NN_POWER_MAX_K))
+    return NN_ERR_ARG;
   if (p->fixed_iter < 0 || p->fixed_iter > kMaxFactors) return NN_ERR_ARG;
   if (p->fixed_iter == 0 && (!(p->tol >= 0.0) || p->max_iter < 1 || p->max_iter > kMaxFactors))
     return NN_ERR_ARG;
@@ -151,13 +155,8 @@ nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const voi
 
   HIP_TRY(hipEventRecord(ctx->ev_start, s));
   // phi (the start iterate) and its scale
-  if (prm->x0 == NN_X0_TRANSPOSE) {
-    HIP_TRY(launch_den_transpose(dt, A, lda, n, w.denpart, w.scal, s));
-    HIP_TRY(launch_x0_transpose(dt, A, lda, w.phi, n, n, w.scal, s));
-  } else {
-    HIP_TRY(launch_den_trace(dt, A, lda, n, w.scal, s));
-    HIP_TRY(launch_x0_identity(dt, w.phi, n, n, w.scal, s));
-  }
+  HIP_TRY(launch_start(dt, prm->x0, prm->power_k, A, lda, w.phi, n, n, w.denpart, w.pw, w.scal,
+                       s));
   HIP_TRY(launch_sumsq(B, is_double(dt), cm * ldb, n, rr, w.part, w.scal + 1, s));
   HIP_TRY(hipMemcpyAsync(ctx->host, w.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -98,6 +98,15 @@ hipError_t launch_x0_transpose(nn_dtype dt, const void* A, int64_t lda, void* X,
 hipError_t launch_x0_identity(nn_dtype dt, void* X, int64_t ldx, int64_t n, const double* scal,
                               hipStream_t s);
 
+// Start iterate X_0 for every x0 choice except NN_X0_GIVEN (nn_start.hip):
+// the scale den lands in scal[0] (not finite: NONFINITE; <= 0: DIVERGED).
+// denpart: den_partials_elems(n) doubles; pw: start_scratch_doubles(n).
+constexpr int kPowerMaxK = 64;
+size_t start_scratch_doubles(int64_t n);
+hipError_t launch_start(nn_dtype dt, int x0, int power_k, const void* A, int64_t lda, void* X,
+                        int64_t ldx, int64_t n, double* denpart, double* pw, double* scal,
+                        hipStream_t s);
+
 // Sum `count` FP64 partials in a fixed order; out[0] <- sqrt(sum / n_rows).
 hipError_t launch_rms_reduce(const double* partials, int count, int64_t n_rows, double* out,
                              hipStream_t s);

@@ -29,6 +29,8 @@ NN_ERR_ARG, NN_ERR_DIVERGED, NN_ERR_NONFINITE = -1, -2, -3
 NN_ERR_HIP, NN_ERR_WORKSPACE, NN_ERR_UNSUPPORTED = -4, -5, -6
 NN_F64, NN_F32, NN_C64, NN_C128 = 0, 1, 2, 3
 NN_X0_TRANSPOSE, NN_X0_SCALED_IDENTITY, NN_X0_GIVEN = 0, 1, 2
+NN_X0_TRANSPOSE_FROB, NN_X0_POWER_IDENTITY, NN_X0_POWER_TRANSPOSE, NN_X0_JACOBI = 3, 4, 5, 6
+NN_POWER_MAX_K = 64
 NN_PREC_PLAIN, NN_PREC_MIXED = 0, 1
 NN_MAX_DEPTH = 8
 NN_TRACE_MAX = 128
@@ -36,13 +38,16 @@ NN_FLAG_TIME_GEMMS = 1
 NN_CNS_MAX_TERMS = 1000000
 
 X0_NAMES = {"transpose": NN_X0_TRANSPOSE, "identity": NN_X0_SCALED_IDENTITY,
-            "scaled_identity": NN_X0_SCALED_IDENTITY, "given": NN_X0_GIVEN}
+            "scaled_identity": NN_X0_SCALED_IDENTITY, "given": NN_X0_GIVEN,
+            "transpose_frob": NN_X0_TRANSPOSE_FROB, "power_identity": NN_X0_POWER_IDENTITY,
+            "power_transpose": NN_X0_POWER_TRANSPOSE, "jacobi": NN_X0_JACOBI}
 
 
 class nn_params(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("x0", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("fixed_iter", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("power_k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class nn_info(ctypes.Structure):
@@ -157,7 +162,7 @@ class NNError(RuntimeError):
 
 
 def make_params(depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, prec="plain",
-                flags=0):
+                flags=0, power_k=8):
     if isinstance(x0, str):
         x0 = X0_NAMES[x0]
     p = nn_params()
@@ -165,6 +170,8 @@ def make_params(depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, 
     p.fixed_iter = int(fixed_iter)
     p.prec = NN_PREC_MIXED if prec in ("mixed", NN_PREC_MIXED) else NN_PREC_PLAIN
     p.flags = int(flags)
+    p.power_k = int(power_k)
+    p.reserved = 0
     return p
 
 
@@ -235,7 +242,7 @@ def workspace(nbytes: int, device) :
 
 
 def invert(A, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, prec="plain",
-           X=None, ctx: Context | None = None, ws=None, check=True, flags=0):
+           X=None, ctx: Context | None = None, ws=None, check=True, flags=0, power_k=8):
     """X ~ A^-1 by nn_invert.  Returns (X, info dict).
 
     A: square CUDA tensor (float64, float32, complex64, complex128), row-major
@@ -247,7 +254,7 @@ def invert(A, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, pr
         raise ValueError("A must be a square row-major matrix")
     n = A.shape[0]
     dt = dtype_code(A)
-    prm = make_params(depth, x0, tol, max_iter, fixed_iter, prec, flags)
+    prm = make_params(depth, x0, tol, max_iter, fixed_iter, prec, flags, power_k)
     if X is None:
         X = torch.empty((n, n), dtype=A.dtype, device=A.device)
     elif X.shape != A.shape or X.dtype != A.dtype or X.stride(1) != 1:
@@ -274,12 +281,12 @@ def invert(A, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, pr
 
 
 def solve(A, B, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0,
-          ctx: Context | None = None, check=True):
+          ctx: Context | None = None, check=True, power_k=8):
     """Xsol with A Xsol = B by nn_solve (Corollary 3).  Returns (Xsol, info)."""
     torch = _torch()
     n, nrhs = B.shape
     dt = dtype_code(A)
-    prm = make_params(depth, x0, tol, max_iter, fixed_iter)
+    prm = make_params(depth, x0, tol, max_iter, fixed_iter, power_k=power_k)
     Xs = torch.empty((n, nrhs), dtype=A.dtype, device=A.device)
     ctx = ctx or default_context(A.device.index or 0)
     need = nn_solve_workspace_size(n, nrhs, dt, ctypes.byref(prm))
@@ -302,14 +309,14 @@ def solve(A, B, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0,
 
 
 def solve_factorized(A, B, x0="transpose", tol=1e-10, max_factors=60, fixed_factors=0,
-                     ctx: Context | None = None, check=True):
+                     ctx: Context | None = None, check=True, power_k=8):
     """Xsol with A Xsol = B by nn_solve_factorized (Corollary 6 applied to B).
     Returns (Xsol, info); info["iters"] is the number of factors and
     info["rms"] the relative residual ||B - A Xsol||_F / ||B||_F."""
     torch = _torch()
     n, nrhs = B.shape
     dt = dtype_code(A)
-    prm = make_params(1, x0, tol, max_factors, fixed_factors)
+    prm = make_params(1, x0, tol, max_factors, fixed_factors, power_k=power_k)
     Xs = torch.empty((n, nrhs), dtype=A.dtype, device=A.device)
     ctx = ctx or default_context(A.device.index or 0)
     need = nn_solve_factorized_workspace_size(n, nrhs, dt, ctypes.byref(prm))
@@ -333,9 +340,10 @@ def solve_factorized(A, B, x0="transpose", tol=1e-10, max_factors=60, fixed_fact
 
 
 def make_cns_params(depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nests=100,
-                    prec="plain", tol=1e-12, max_terms=100, fixed_terms=None, reuse_phi=False):
+                    prec="plain", tol=1e-12, max_terms=100, fixed_terms=None, reuse_phi=False,
+                    power_k=8):
     c = nn_cns_params()
-    c.precond = make_params(depth, x0, precond_tol, max_nests, nests, prec)
+    c.precond = make_params(depth, x0, precond_tol, max_nests, nests, prec, power_k=power_k)
     c.tol = float(tol)
     c.max_terms = int(max_terms)
     c.fixed_terms = -1 if fixed_terms is None else int(fixed_terms)
@@ -346,7 +354,7 @@ def make_cns_params(depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nest
 
 def solve_cns(A, B, depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nests=100,
               prec="plain", tol=1e-12, max_terms=100, fixed_terms=None, ws=None,
-              reuse_phi=False, ctx: Context | None = None, check=True):
+              reuse_phi=False, ctx: Context | None = None, check=True, power_k=8):
     """Xsol with A Xsol = B by nn_solve_cns: NN nests for phi (``nests`` > 0
     fixed, else down to rms < precond_tol), then the Neumann series in
     I - phi A applied to B (``fixed_terms`` terms, else down to the relative
@@ -361,7 +369,7 @@ def solve_cns(A, B, depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nest
     n, nrhs = B.shape
     dt = dtype_code(A)
     prm = make_cns_params(depth, x0, nests, precond_tol, max_nests, prec, tol, max_terms,
-                          fixed_terms, reuse_phi)
+                          fixed_terms, reuse_phi, power_k)
     Xs = torch.empty((n, nrhs), dtype=A.dtype, device=A.device)
     ctx = ctx or default_context(A.device.index or 0)
     need = nn_solve_cns_workspace_size(n, nrhs, dt, ctypes.byref(prm))

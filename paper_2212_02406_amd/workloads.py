@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "rng", "spectrum_uniform", "spectrum_loguniform", "haar_unitary",
     "dense_spd", "mimo_gram_batch", "pack_batch", "serving_pool",
-    "ragged_batch",
+    "ragged_batch", "mimo_gram", "diag_dominant",
 ]
 
 
@@ -140,6 +140,35 @@ def mimo_gram_batch(batch: int = 4096, M: int = 128, Ks=(8, 16, 32, 64),
         mats.append(G.astype(dtype))
     packed, offsets, sizes = pack_batch(mats, dtype)
     return packed, offsets, sizes, mats
+
+
+def mimo_gram(M: int, K: int, seed: int, sigma2: float = 0.1, complex_: bool = True,
+              dtype=np.complex128):
+    """One massive-MIMO regularised Gram matrix G = H^H H + sigma^2 I, H of
+    shape M x K with iid CN(0,1) (N(0,1) if not complex_) entries.  With
+    M >> K its spectrum over diag(G) lies near [(1 - sqrt(K/M))^2,
+    (1 + sqrt(K/M))^2]."""
+    g = rng(seed)
+    H = _gaussian(M, K, g, complex_)
+    G = H.conj().T @ H + sigma2 * np.eye(K)
+    G = 0.5 * (G + G.conj().T)
+    return G.astype(dtype)
+
+
+def diag_dominant(n: int, seed: int, complex_: bool = False, dtype=None, margin: float = 1.0):
+    """Hermitian, strictly diagonally dominant, positive diagonal: off-diagonal
+    entries uniform in [-1, 1) (real and imaginary parts), a_ii = sum_j |a_ij|
+    + margin.  Such a matrix is positive definite."""
+    g = rng(seed)
+    E = g.uniform(-1.0, 1.0, (n, n))
+    if complex_:
+        E = E + 1j * g.uniform(-1.0, 1.0, (n, n))
+    E = 0.5 * (E + E.conj().T)
+    np.fill_diagonal(E, 0.0)
+    A = E + np.diag(np.abs(E).sum(axis=1) + margin)
+    if dtype is None:
+        dtype = np.complex128 if complex_ else np.float64
+    return A.astype(dtype)
 
 
 def ragged_batch(sizes, seed: int, lo: float = 1.0, hi: float = 100.0,

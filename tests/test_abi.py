@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
 
 def test_struct_layout():
     nn = _nn()
-    assert ctypes.sizeof(nn.nn_params) == 32
+    assert ctypes.sizeof(nn.nn_params) == 40 and nn.nn_params.power_k.offset == 32
     assert nn.nn_info.rms_trace.offset == 48
     assert ctypes.sizeof(nn.nn_info) == 48 + 8 * nn.NN_TRACE_MAX
     assert ctypes.sizeof(nn.nn_info_dev) == 16
@@ -37,8 +37,8 @@ def test_struct_layout():
     assert ctypes.sizeof(nn.nn_request_info) == 64
     assert nn.nn_request_info.rms.offset == 32
     assert ctypes.sizeof(nn.nn_server_stats) == 24
-    assert ctypes.sizeof(nn.nn_cns_params) == 56
-    assert nn.nn_cns_params.tol.offset == 32 and nn.nn_cns_params.reuse_phi.offset == 48
+    assert ctypes.sizeof(nn.nn_cns_params) == 64
+    assert nn.nn_cns_params.tol.offset == 40 and nn.nn_cns_params.reuse_phi.offset == 56
 
 
 def test_server_argument_errors_before_device_work():
