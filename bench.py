@@ -1,7 +1,7 @@
 """Benchmark of the NN inversion on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--no-extras | --legs fp32,factorized,cns,batched,mixed,serving]
+                    [--no-extras | --legs fp32,factorized,cns,starts,batched,mixed,serving]
 
 A step is one whole inversion through the C ABI: start-iterate prologue, then
 nests of d + 1 GEMMs until rms = ||I - A X||_F / sqrt(N) < tol.  The headline
@@ -24,7 +24,9 @@ GEMM source), the oracle timed on the host on a bounded sample, and under
   factorized  A X = B (64 right-hand sides) on the headline matrix with the
            factorised series of Corollary 6, against nn_solve;
   cns      the same system by the Chebyshev-Neumann series (plain and mixed
-           nests for the preconditioner), against nn_solve.
+           nests for the preconditioner), against nn_solve;
+  starts   the other start iterates (Frobenius and power-iteration scales,
+           Jacobi on a massive-MIMO Gram matrix) against the default ones.
 """
 import argparse
 import json
@@ -53,7 +55,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp32,factorized,cns,batched,mixed,serving",
+    ap.add_argument("--legs", default="fp32,factorized,cns,starts,batched,mixed,serving",
                     help="comma list of extra workloads to run")
     ap.add_argument("--mixed-n", type=int, default=16384)
     ap.add_argument("--serve-pool", type=int, default=64)
@@ -336,6 +338,37 @@ def leg_cns(nn, torch, workloads, np, A, n):
     return out
 
 
+def leg_starts(nn, torch, workloads, np, A, n):
+    """The other normalisations (start iterates) on the headline matrix, each
+    to rms 1e-12: the ||A||_1 ||A||_inf and ||A||_F^2 transpose scales,
+    Theta_2(8) A^H (power iteration on A A^H), I / Tr A and Theta_2(8) I.
+    Then a massive-MIMO Gram matrix (1024 users, 8192 antennas, complex128,
+    sigma^2 0.1) with the Jacobi start diag(G)^-1 against I / Tr G and
+    Theta_2(8) I."""
+    def run(M, x0, **kw):
+        nn.invert(M, x0=x0, tol=1e-12, max_iter=100, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = nn.invert(M, x0=x0, tol=1e-12, max_iter=100, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        return {"s": t, "inverses_per_s": 1.0 / t, "nests": info["iters"], "gemms": info["gemms"],
+                "rms": info["rms"], "status": info["status"]}
+
+    out = {"headline": {}, "mimo_gram": {}}
+    for x0, kw in (("transpose", {}), ("transpose_frob", {}), ("power_transpose", {"power_k": 8}),
+                   ("identity", {}), ("power_identity", {"power_k": 8})):
+        out["headline"][x0] = run(A, x0, **kw)
+        log(f"starts leg headline {x0}: {out['headline'][x0]}")
+    G = torch.from_numpy(workloads.mimo_gram(8192, 1024, 11)).cuda()
+    for x0, kw in (("identity", {}), ("power_identity", {"power_k": 8}), ("jacobi", {})):
+        out["mimo_gram"][x0] = run(G, x0, **kw)
+        log(f"starts leg mimo_gram {x0}: {out['mimo_gram'][x0]}")
+    out["workload"] = (f"headline: dense SPD N={n} FP64 cond 1e3 seed 2, d=2, tol rms 1e-12; "
+                       "mimo_gram: G = H^H H + 0.1 I, H 8192 x 1024 CN(0,1) seed 11, complex128")
+    return out
+
+
 def leg_serving(nn, torch, workloads, np, pool_size, n_req):
     """Poisson request stream over a pool of FP32 SPD / complex64 HPD
     matrices, N log-uniform in [32, 4096], cond log-uniform in [10, 1e4],
@@ -502,6 +535,9 @@ def main():
         extra["factorized"] = leg_factorized(nn, torch, workloads, np, A, n)
     if "cns" in legs:
         extra["cns"] = leg_cns(nn, torch, workloads, np, A, n)
+        torch.cuda.empty_cache()
+    if "starts" in legs:
+        extra["starts"] = leg_starts(nn, torch, workloads, np, A, n)
         torch.cuda.empty_cache()
     if legs & {"batched", "mixed", "serving"}:
         del X
