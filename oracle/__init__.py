@@ -15,6 +15,8 @@ via GPU acceleration", arXiv 2212.02406):
                  applied to a right-hand side (A x = B without forming X).
 * ``nn_fp64.nn_cns_solve_ref`` — the Chebyshev-Neumann series: NN nests as
                  the preconditioner of a Neumann series applied to B.
+* ``nn_sparse.nn_sparse_solve_ref`` — the sparse form (Algorithm 2): the
+                 Neumann series in P = I - phi W applied to phi B for CSR W.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import or run anything in here.  The product path (the HIP
@@ -35,3 +37,4 @@ from .nn_fp64 import (  # noqa: F401
     norm_1, norm_inf, initial_guess, residual, rms_of, nn_step, nn_ref,
     nn_solve_ref, nn_factorized_solve_ref, nn_cns_solve_ref, nn_batched_ref,
 )
+from .nn_sparse import nn_sparse_solve_ref, sparse_preconditioner  # noqa: F401,E402

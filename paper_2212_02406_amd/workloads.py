@@ -30,7 +30,8 @@ import numpy as np
 __all__ = [
     "rng", "spectrum_uniform", "spectrum_loguniform", "haar_unitary",
     "dense_spd", "mimo_gram_batch", "pack_batch", "serving_pool",
-    "ragged_batch", "mimo_gram", "diag_dominant",
+    "ragged_batch", "mimo_gram", "diag_dominant", "laplacian_2d", "random_sparse_hpd",
+    "csr_to_dense",
 ]
 
 
@@ -208,3 +209,82 @@ def build_request(entry, device=None):
     dtype = np.complex64 if entry["complex"] else np.float32
     return dense_spd(entry["n"], 1.0, entry["cond"], entry["seed"], log_spectrum=True,
                      complex_=entry["complex"], dtype=dtype, device=device)
+
+
+def laplacian_2d(nx: int, ny: int, shift: float = 0.5, dtype=np.float64):
+    """CSR arrays of the 5-point Laplacian on an nx x ny grid (Dirichlet
+    boundary, natural row-major ordering: node (i, j) is row i * ny + j) plus
+    shift * I: diagonal 4 + shift, -1 for each grid neighbour.  Its
+    eigenvalues are 4 + shift - 2 cos(pi p / (nx + 1)) - 2 cos(pi q / (ny + 1)),
+    p = 1..nx, q = 1..ny, with eigenvectors sin(pi p (i+1) / (nx+1))
+    sin(pi q (j+1) / (ny+1)).  Returns (indptr int32, indices int32, values)."""
+    n = nx * ny
+    i, j = np.divmod(np.arange(n, dtype=np.int64), ny)
+    cols, vals = [], []
+    for di, dj, v in ((-1, 0, -1.0), (0, -1, -1.0), (0, 0, 4.0 + shift), (0, 1, -1.0),
+                      (1, 0, -1.0)):
+        ii, jj = i + di, j + dj
+        ok = (ii >= 0) & (ii < nx) & (jj >= 0) & (jj < ny)
+        c = np.where(ok, ii * ny + jj, -1)
+        cols.append(c)
+        vals.append(np.where(ok, v, 0.0))
+    C = np.stack(cols, axis=1)          # n x 5, columns already ascending
+    V = np.stack(vals, axis=1)
+    keep = C >= 0
+    counts = keep.sum(axis=1)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    indices = C[keep].astype(np.int32)
+    values = V[keep].astype(dtype)
+    return indptr.astype(np.int32), indices, values
+
+
+def random_sparse_hpd(n: int, seed: int, deg_lo: int = 1, deg_hi: int = 32,
+                      complex_: bool = False, dtype=None, margin: float = 1.0):
+    """CSR arrays of a random Hermitian, strictly diagonally dominant sparse
+    matrix with an uneven row-length mix: row r draws an off-diagonal count
+    uniform in [deg_lo, deg_hi] and that many random columns with values
+    uniform in [-1, 1) (+ i [-1, 1)); the pattern is symmetrised (conjugate
+    values), and a_rr = sum of the row's |a_rc| + margin."""
+    g = rng(seed)
+    deg = g.integers(deg_lo, deg_hi + 1, size=n)
+    rows = np.repeat(np.arange(n), deg)
+    cols = g.integers(0, n, size=rows.size)
+    v = g.uniform(-1.0, 1.0, rows.size)
+    if complex_:
+        v = v + 1j * g.uniform(-1.0, 1.0, rows.size)
+    off = rows != cols
+    rows, cols, v = rows[off], cols[off], v[off]
+    # symmetrise: (r, c, v) and (c, r, conj v); duplicates are summed
+    R = np.concatenate([rows, cols])
+    Cc = np.concatenate([cols, rows])
+    Vv = np.concatenate([v, np.conj(v)]) * 0.5
+    key = R.astype(np.int64) * n + Cc
+    order = np.argsort(key, kind="stable")
+    key, Vv = key[order], Vv[order]
+    uniq, start = np.unique(key, return_index=True)
+    vals = np.add.reduceat(Vv, start) if key.size else Vv
+    R, Cc = np.divmod(uniq, n)
+    rowabs = np.zeros(n)
+    np.add.at(rowabs, R, np.abs(vals))
+    # insert the diagonal
+    R = np.concatenate([R, np.arange(n)])
+    Cc = np.concatenate([Cc, np.arange(n)])
+    vals = np.concatenate([vals, (rowabs + margin).astype(vals.dtype)])
+    key = R * n + Cc
+    order = np.argsort(key, kind="stable")
+    R, Cc, vals = R[order], Cc[order], vals[order]
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(indptr, R + 1, 1)
+    np.cumsum(indptr, out=indptr)
+    if dtype is None:
+        dtype = np.complex128 if complex_ else np.float64
+    return indptr.astype(np.int32), Cc.astype(np.int32), vals.astype(dtype)
+
+
+def csr_to_dense(indptr, indices, values, n: int) -> np.ndarray:
+    """The dense n x n matrix of CSR arrays (duplicates summed)."""
+    A = np.zeros((n, n), dtype=values.dtype)
+    rows = np.repeat(np.arange(n), np.diff(indptr.astype(np.int64)))
+    np.add.at(A, (rows, indices.astype(np.int64)), values)
+    return A
