@@ -270,6 +270,62 @@ nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, i
                        const nn_cns_params* params, void* ws, size_t ws_bytes,
                        nn_info* precond_info, nn_info* info, double* rel_residual);
 
+/* Parameters of nn_solve_sparse. */
+typedef struct {
+  int32_t x0;          /* NN_X0_SCALED_IDENTITY (phi = I / Re Tr W),
+                          NN_X0_POWER_IDENTITY (phi = Theta_2(power_k) I) or
+                          NN_X0_JACOBI (phi = diag(W)^-1) */
+  int32_t power_k;     /* NN_X0_POWER_IDENTITY: 1..NN_POWER_MAX_K */
+  double tol;          /* tolerance mode: stop when the control residual
+                          (below) is < tol (>= 0) */
+  int32_t max_terms;   /* tolerance mode: at most this many terms,
+                          1..NN_SPARSE_MAX_TERMS */
+  int32_t fixed_terms; /* >= 0: exactly this many terms; -1: tolerance mode */
+  int32_t check_every; /* tolerance mode: terms enqueued between host reads
+                          of the device-side control block, 1..1024 */
+  int32_t reserved;    /* must be 0 */
+} nn_sparse_params;
+
+#define NN_SPARSE_MAX_TERMS 100000000
+
+/* Workspace bytes nn_solve_sparse needs (0 on bad arguments). */
+size_t nn_solve_sparse_workspace_size(int64_t n, int64_t nrhs, nn_dtype dtype,
+                                      const nn_sparse_params* params);
+
+/* Solve W Xsol = B for a sparse W with the Neumann series in P = I - phi W
+ * applied to phi B, never storing a power of P (Algorithm 2; Corollary 6 and
+ * the sparse-system passage after it; with T = (L+1)^i - 1 terms it is i NN
+ * nests of depth L applied to B, Corollary 2):
+ *     Xsol = sum_{m=0}^{T} P^m phi B.
+ * The device evaluates it in Horner form, one fused sparse step per term:
+ *     r_t = B - W x_t,   x_{t+1} = x_t + phi r_t,   x_0 = phi B,
+ * with the sums of w_r |r_rc|^2 and |r_rc|^2 fused (w_r = |phi_r|).  phi is a
+ * scalar or a diagonal, so sparsity is kept.
+ *   W: CSR with int32 row_ptr[n + 1] (row_ptr[0] = 0, non-decreasing,
+ *     row_ptr[n] = nnz), int32 col_idx[nnz] in [0, n), values[nnz] of dtype
+ *     (duplicates are summed).  The structure is checked on the device before
+ *     any product (NN_ERR_ARG if it is not valid CSR).
+ *   Control: the phi-weighted relative residual
+ *     ||w^(1/2) (B - W x)||_F / ||w^(1/2) B||_F (the plain relative residual
+ *     for a scalar phi), in which the iteration contracts for Hermitian PD W
+ *     (diagonal dominance for the Jacobi start).  fixed_terms >= 0: exactly
+ *     that many terms; tolerance mode: the rules of nn_solve_factorized with
+ *     max_terms.  The rules run on the device after every term; the host reads
+ *     the outcome every check_every terms (steps enqueued after the stop do
+ *     no work), so there is no host synchronisation per term.
+ *   info (optional): iters = terms of the returned Xsol, rms = its control
+ *     residual, gemms = sparse steps that ran, trace = control residuals after
+ *     0, 1, ... terms.  *rel_residual (optional) = plain
+ *     ||B - W Xsol||_F / ||B||_F.
+ * B (n x nrhs, ldb) and Xsol (n x nrhs, ldx) are dense device arrays; Xsol
+ * must not alias B, the CSR arrays or the workspace.  Supported: F64, F32,
+ * C64, C128 (products accumulate in the dtype; norms in FP64). */
+nn_status nn_solve_sparse(nn_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx,
+                          const void* values, int64_t n, int64_t nnz, const void* B, int64_t ldb,
+                          void* Xsol, int64_t ldx, int64_t nrhs, nn_dtype dtype,
+                          const nn_sparse_params* params, void* ws, size_t ws_bytes,
+                          nn_info* info, double* rel_residual);
+
 /* Workspace bytes nn_invert_batched needs for `batch` matrices. */
 size_t nn_batched_workspace_size(int32_t batch, nn_dtype dtype);
 

@@ -107,6 +107,12 @@ hipError_t launch_start(nn_dtype dt, int x0, int power_k, const void* A, int64_t
                         int64_t ldx, int64_t n, double* denpart, double* pw, double* scal,
                         hipStream_t s);
 
+// The SplitMix64 power-iteration vector (real values; zero imaginary parts
+// when cplx) and its squared entries; out[0] = mult * sqrt(sum part[0..count)).
+hipError_t launch_power_vector(bool cplx, double* x, double* rowsq, int64_t n, hipStream_t s);
+hipError_t launch_norm_reduce(const double* part, int64_t count, double mult, double* out,
+                              hipStream_t s);
+
 // Sum `count` FP64 partials in a fixed order; out[0] <- sqrt(sum / n_rows).
 hipError_t launch_rms_reduce(const double* partials, int count, int64_t n_rows, double* out,
                              hipStream_t s);

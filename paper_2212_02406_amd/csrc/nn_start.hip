@@ -268,6 +268,21 @@ hipError_t jacobi_start(const void* A, int64_t lda, void* X, int64_t ldx, int64_
 
 }  // namespace
 
+hipError_t launch_power_vector(bool cplx, double* x, double* rowsq, int64_t n, hipStream_t s) {
+  const unsigned gb = (unsigned)((n + 255) / 256);
+  if (cplx)
+    hipLaunchKernelGGL((power_init<true>), dim3(gb), dim3(256), 0, s, x, rowsq, n);
+  else
+    hipLaunchKernelGGL((power_init<false>), dim3(gb), dim3(256), 0, s, x, rowsq, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_reduce(const double* part, int64_t count, double mult, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(norm_reduce, dim3(1), dim3(256), 0, s, part, count, mult, out);
+  return hipGetLastError();
+}
+
 size_t start_scratch_doubles(int64_t n) {
   const int64_t nchunks = (n + kChunk - 1) / kChunk;
   return (size_t)(7 * n + kPowerMaxK + 8 + nchunks * 2 * n + 256);

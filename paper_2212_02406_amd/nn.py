@@ -36,6 +36,7 @@ NN_MAX_DEPTH = 8
 NN_TRACE_MAX = 128
 NN_FLAG_TIME_GEMMS = 1
 NN_CNS_MAX_TERMS = 1000000
+NN_SPARSE_MAX_TERMS = 100000000
 
 X0_NAMES = {"transpose": NN_X0_TRANSPOSE, "identity": NN_X0_SCALED_IDENTITY,
             "scaled_identity": NN_X0_SCALED_IDENTITY, "given": NN_X0_GIVEN,
@@ -68,6 +69,12 @@ class nn_cns_params(ctypes.Structure):
     _fields_ = [("precond", nn_params), ("tol", ctypes.c_double), ("max_terms", ctypes.c_int32),
                 ("fixed_terms", ctypes.c_int32), ("reuse_phi", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class nn_sparse_params(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int32), ("power_k", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_terms", ctypes.c_int32), ("fixed_terms", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class nn_info_dev(ctypes.Structure):
@@ -117,6 +124,11 @@ _SIGS = {
                                     ctypes.POINTER(nn_cns_params), _p, _sz,
                                     ctypes.POINTER(nn_info), ctypes.POINTER(nn_info),
                                     ctypes.POINTER(ctypes.c_double)]),
+    "nn_solve_sparse_workspace_size": (_sz, [_i64, _i64, ctypes.c_int,
+                                             ctypes.POINTER(nn_sparse_params)]),
+    "nn_solve_sparse": (ctypes.c_int, [_p, _p, _p, _p, _i64, _i64, _p, _i64, _p, _i64, _i64,
+                                       ctypes.c_int, ctypes.POINTER(nn_sparse_params), _p, _sz,
+                                       ctypes.POINTER(nn_info), ctypes.POINTER(ctypes.c_double)]),
     "nn_batched_workspace_size": (_sz, [_i32, ctypes.c_int]),
     "nn_invert_batched": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
                                          _sz, _p]),
@@ -393,6 +405,70 @@ def solve_cns(A, B, depth=2, x0="transpose", nests=0, precond_tol=1e-2, max_nest
     d["ws"] = ws
     if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
         raise NNError(st, "nn_solve_cns")
+    return Xs, d
+
+
+def make_sparse_params(x0="identity", power_k=8, tol=1e-10, max_terms=100000,
+                       fixed_terms=None, check_every=16):
+    if isinstance(x0, str):
+        x0 = X0_NAMES[x0]
+    p = nn_sparse_params()
+    p.x0, p.power_k, p.tol = int(x0), int(power_k), float(tol)
+    p.max_terms = int(max_terms)
+    p.fixed_terms = -1 if fixed_terms is None else int(fixed_terms)
+    p.check_every = int(check_every)
+    p.reserved = 0
+    return p
+
+
+def solve_sparse(indptr, indices, values, B, x0="identity", power_k=8, tol=1e-10,
+                 max_terms=100000, fixed_terms=None, check_every=16, ctx: Context | None = None,
+                 ws=None, check=True):
+    """Xsol with W Xsol = B for a CSR matrix W by nn_solve_sparse (the
+    Neumann series in I - phi W applied to phi B, Algorithm 2).  indptr and
+    indices: int32 CUDA tensors; values and B: CUDA tensors of one dtype.
+    Returns (Xsol, info): info["iters"] = terms, info["rms"] = control
+    residual, info["rel_residual"] = plain ||B - W Xsol||_F / ||B||_F."""
+    torch = _torch()
+    if indptr.dtype != torch.int32 or indices.dtype != torch.int32:
+        raise TypeError("indptr and indices must be int32")
+    if values.dtype != B.dtype:
+        raise TypeError("values and B must share a dtype")
+    if B.dim() != 2 or B.stride(1) != 1:
+        raise ValueError("B must be a row-major matrix")
+    n, nrhs = B.shape
+    if indptr.numel() != n + 1:
+        raise ValueError("indptr must have n + 1 entries")
+    nnz = indices.numel()
+    if values.numel() != nnz:
+        raise ValueError("values and indices must have nnz entries")
+    dt = dtype_code(B)
+    prm = make_sparse_params(x0, power_k, tol, max_terms, fixed_terms, check_every)
+    Xs = torch.empty((n, nrhs), dtype=B.dtype, device=B.device)
+    ctx = ctx or default_context(B.device.index or 0)
+    need = nn_solve_sparse_workspace_size(n, nrhs, dt, ctypes.byref(prm))
+    if need == 0:
+        raise NNError(NN_ERR_ARG, "nn_solve_sparse_workspace_size")
+    hold = None
+    if ws is None:
+        hold, ws_ptr, ws_bytes = workspace(need, B.device)
+    else:
+        hold, ws_ptr, ws_bytes = ws
+    info = nn_info()
+    rel = ctypes.c_double(0.0)
+    st = nn_solve_sparse(ctx.ptr, ctypes.c_void_p(indptr.data_ptr()),
+                         ctypes.c_void_p(indices.data_ptr() if nnz else 0),
+                         ctypes.c_void_p(values.data_ptr() if nnz else 0), n, nnz,
+                         ctypes.c_void_p(B.data_ptr()), B.stride(0),
+                         ctypes.c_void_p(Xs.data_ptr()), Xs.stride(0), nrhs, dt,
+                         ctypes.byref(prm), ctypes.c_void_p(ws_ptr), ws_bytes,
+                         ctypes.byref(info), ctypes.byref(rel))
+    del hold
+    d = info.as_dict()
+    d["status"] = st
+    d["rel_residual"] = rel.value
+    if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
+        raise NNError(st, "nn_solve_sparse")
     return Xs, d
 
 

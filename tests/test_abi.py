@@ -37,6 +37,7 @@ def test_struct_layout():
     assert ctypes.sizeof(nn.nn_request_info) == 64
     assert nn.nn_request_info.rms.offset == 32
     assert ctypes.sizeof(nn.nn_server_stats) == 24
+    assert ctypes.sizeof(nn.nn_sparse_params) == 32 and nn.nn_sparse_params.tol.offset == 8
     assert ctypes.sizeof(nn.nn_cns_params) == 64
     assert nn.nn_cns_params.tol.offset == 40 and nn.nn_cns_params.reuse_phi.offset == 56
 
@@ -107,6 +108,31 @@ def test_cns_argument_errors_and_workspace():
     assert sz(nn.make_cns_params(prec="mixed", x0="identity")) > 0
     assert sz(nn.make_cns_params(prec="mixed", x0="identity"), dt=nn.NN_F32) == 0
     assert sz(ok, n=0) == 0 and sz(ok, r=0) == 0 and sz(ok, dt=7) == 0
+
+
+def test_sparse_argument_errors_and_workspace():
+    nn = _nn()
+    fake = ctypes.c_void_p(0x1000)
+    inf = nn.nn_info()
+    ok = nn.make_sparse_params()
+    assert nn.nn_solve_sparse(None, fake, fake, fake, 4, 4, fake, 1, fake, 1, 1, nn.NN_F64,
+                              ctypes.byref(ok), fake, 1 << 20, ctypes.byref(inf),
+                              None) == nn.NN_ERR_ARG
+    sz = lambda c, n=1000, r=16, dt=nn.NN_F64: nn.nn_solve_sparse_workspace_size(
+        n, r, dt, ctypes.byref(c))
+    base = sz(ok)
+    assert base >= 2 * 1000 * 16 * 8
+    assert sz(ok, r=32) > base and sz(ok, dt=nn.NN_C128) > base
+    for bad in (nn.make_sparse_params(x0="transpose"), nn.make_sparse_params(x0="given"),
+                nn.make_sparse_params(tol=-1.0), nn.make_sparse_params(max_terms=0),
+                nn.make_sparse_params(check_every=0), nn.make_sparse_params(check_every=1025),
+                nn.make_sparse_params(fixed_terms=-2),
+                nn.make_sparse_params(x0="power_identity", power_k=0)):
+        assert sz(bad) == 0
+    c = nn.make_sparse_params()
+    c.reserved = 3
+    assert sz(c) == 0
+    assert sz(nn.make_sparse_params(x0="jacobi", fixed_terms=0, check_every=0)) > 0
 
 
 def test_workspace_sizes_grow_with_depth_and_n():

@@ -1,0 +1,202 @@
+"""Parity of nn_solve_sparse (the Neumann series in P = I - phi W applied to
+phi B for CSR W, Algorithm 2) with the sparse oracle.
+
+The oracle evaluates 2^s - 1 terms by Algorithm 2's factorised loop and
+other counts term by term; the device runs the Horner form (one fused sparse
+step per term).  Same polynomial in W applied to B, so:
+* fixed terms: FP64 / complex128 relative Frobenius <= 1e-10 against the
+  oracle on ragged random sparse HPD matrices (uneven row lengths), every
+  lane-group width (nrhs 1 .. 100), padded leading dimensions, three starts;
+* tolerance mode: x - W^-1 B = -W^-1 r, so the device and oracle solutions
+  agree within kappa (rel + rel_oracle); single precision adds the forward
+  error of a single-precision solve, 64 u32 kappa;
+* the device-side stopping rules give the same result for every
+  check_every (bitwise);
+* full size: the 5-point Laplacian on a 2048 x 2048 grid (+0.5 I, 4.2 M rows,
+  21 M nonzeros) with 16 sine eigenvectors as right-hand sides, against the
+  spectral closed form (1 - (1 - theta lam)^(T+1)) / lam.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.nn_sparse import nn_sparse_solve_ref
+from paper_2212_02406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+from paper_2212_02406_amd import nn  # noqa: E402
+
+DEV = torch.device("cuda:0")
+U32 = 2.0 ** -24
+X0 = {"identity": oracle.X0_SCALED_IDENTITY, "power_identity": oracle.X0_POWER_IDENTITY,
+      "jacobi": oracle.X0_JACOBI}
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _relF(X, Y):
+    return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
+
+
+def _dev(a, ld=None):
+    a = np.ascontiguousarray(a)
+    if ld is None or a.ndim == 1 or ld == a.shape[1]:
+        return torch.from_numpy(a).to(DEV)
+    big = np.zeros((a.shape[0], ld), dtype=a.dtype)
+    big[:, :a.shape[1]] = a
+    return torch.from_numpy(big).to(DEV)[:, :a.shape[1]]
+
+
+def _case(n, nrhs, seed, dtype, deg_hi=24):
+    cplx = np.dtype(dtype).kind == "c"
+    ip, ix, v = W.random_sparse_hpd(n, seed, deg_hi=deg_hi, complex_=cplx, dtype=dtype)
+    g = W.rng(seed + 1)
+    B = g.standard_normal((n, nrhs)) + (1j * g.standard_normal((n, nrhs)) if cplx else 0.0)
+    return ip, ix, v, B.astype(dtype)
+
+
+def _solve(ip, ix, v, B, ldb=None, **kw):
+    return nn.solve_sparse(_dev(ip), _dev(ix), _dev(v), _dev(B, ldb), **kw)
+
+
+@pytest.mark.parametrize("n,nrhs,ldb", [(1, 1, 1), (37, 3, 5), (500, 16, 16), (3001, 65, 70),
+                                        (800, 100, 100), (640, 2, 2)])
+@pytest.mark.parametrize("x0", list(X0))
+@pytest.mark.parametrize("dtype", [np.float64, np.complex128])
+def test_fixed_terms_vs_oracle(n, nrhs, ldb, x0, dtype):
+    _say(f"sparse fixed n={n} nrhs={nrhs} ldb={ldb} x0={x0} {np.dtype(dtype).name}")
+    ip, ix, v, B = _case(n, nrhs, 900 + n, dtype)
+    for T in (0, 1, 7, 20):
+        xo, io = nn_sparse_solve_ref(ip, ix, v, B, x0=X0[x0], fixed_terms=T)
+        X, info = _solve(ip, ix, v, B, ldb, x0=x0, fixed_terms=T)
+        torch.cuda.synchronize()
+        assert info["status"] == nn.NN_OK and info["iters"] == T, info["status"]
+        assert _relF(X.cpu().numpy(), xo) < 1e-10, T
+        assert abs(info["rms"] - io["control"]) <= 1e-9 * io["control"] + 1e-14
+        assert abs(info["rel_residual"] - io["rel_residual"]) <= 1e-9 * io["rel_residual"] + 1e-14
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.complex128, np.float32, np.complex64])
+@pytest.mark.parametrize("x0", list(X0))
+def test_tolerance_mode_vs_oracle(x0, dtype):
+    _say(f"sparse tol {x0} {np.dtype(dtype).name}")
+    single = np.dtype(dtype) in (np.dtype(np.float32), np.dtype(np.complex64))
+    # Theta_1 = 1 / Tr W undershoots 1 / lambda_max by about n (Sec. II-A), so
+    # the identity start needs ~n kappa terms: it runs on a smaller matrix
+    n, nrhs = (120 if x0 == "identity" else 2000), 8
+    ip, ix, v, B = _case(n, nrhs, 950, dtype, deg_hi=12)
+    ref_dt = np.complex128 if np.dtype(dtype).kind == "c" else np.float64
+    vd, Bd = v.astype(ref_dt), B.astype(ref_dt)
+    xo, io = nn_sparse_solve_ref(ip, ix, vd, Bd, x0=X0[x0], tol=1e-12, max_terms=100000)
+    assert io["status"] == oracle.OK
+    tol = 1e-5 if single else 1e-12
+    X, info = _solve(ip, ix, v, B, x0=x0, tol=tol)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK, info
+    A = W.csr_to_dense(ip, ix, vd, n)
+    kappa = np.linalg.cond(A)
+    dg = np.abs(np.diag(A))
+    wr = np.sqrt(dg.max() / dg.min()) if x0 == "jacobi" else 1.0
+    x = X.cpu().numpy().astype(ref_dt)
+    bar = kappa * (info["rms"] * wr + io["rel_residual"]) * 1.01
+    if single:
+        bar += 64 * U32 * kappa
+    else:
+        assert abs(info["iters"] - io["terms"]) <= 1
+    assert _relF(x, xo) <= bar
+    # the reported plain residual is the true one, recomputed here in FP64
+    true = np.linalg.norm(Bd - A @ x) / np.linalg.norm(Bd)
+    slack = 4 * 24 * U32 * np.linalg.norm(A) * np.linalg.norm(x) / np.linalg.norm(Bd) if single \
+        else 1e-14
+    assert abs(true - info["rel_residual"]) <= 1e-6 * true + slack
+
+
+def test_check_every_gives_identical_results():
+    _say("sparse check_every")
+    ip, ix, v, B = _case(1500, 4, 960, np.float64)
+    outs = []
+    for every in (1, 7, 64, 1024):
+        X, info = _solve(ip, ix, v, B, x0="jacobi", tol=1e-11, check_every=every)
+        torch.cuda.synchronize()
+        assert info["status"] == nn.NN_OK
+        outs.append((X.cpu().numpy(), info["iters"], info["rms"]))
+    for X, it, r in outs[1:]:
+        assert np.array_equal(X, outs[0][0]) and it == outs[0][1] and r == outs[0][2]
+
+
+def test_statuses_and_invalid_csr():
+    _say("sparse statuses")
+    n = 60
+    ip, ix, v, B = _case(n, 2, 970, np.float64, deg_hi=5)
+    # zero diagonal entry with the Jacobi start
+    z = v.copy()
+    z[ip[5] + np.flatnonzero(ix[ip[5]:ip[6]] == 5)[0]] = 0.0
+    _, info = _solve(ip, ix, z, B, x0="jacobi", check=False)
+    assert info["status"] == nn.NN_ERR_DIVERGED
+    nan = v.copy()
+    nan[7] = np.nan
+    _, info = _solve(ip, ix, nan, B, x0="power_identity", check=False)
+    assert info["status"] == nn.NN_ERR_NONFINITE
+    _, info = _solve(ip, ix, v, B, tol=1e-15, max_terms=3)
+    _, io = nn_sparse_solve_ref(ip, ix, v, B, tol=1e-15, max_terms=3)
+    assert info["status"] == nn.NN_NOT_CONVERGED == io["status"] and info["iters"] == 3
+    X, info = _solve(ip, ix, v, B, x0="jacobi", tol=0.0)
+    _, io = nn_sparse_solve_ref(ip, ix, v, B, x0=oracle.X0_JACOBI, tol=0.0, max_terms=100000)
+    assert info["status"] == nn.NN_STAGNATED == io["status"] and info["rms"] < 1e-14
+    _, info = _solve(ip, ix, -v, B, x0="identity", check=False)
+    assert info["status"] == nn.NN_ERR_DIVERGED
+    # a zero right-hand side: control 0 after phi B
+    X, info = _solve(ip, ix, v, np.zeros((n, 2)), tol=1e-12)
+    assert info["status"] == nn.NN_OK and info["iters"] == 0 and float(X.abs().max()) == 0.0
+    # invalid CSR structures are rejected before any product
+    bad_ip = ip.copy()
+    bad_ip[10], bad_ip[11] = bad_ip[11], bad_ip[10] - 1  # decreasing
+    bad_ix = ix.copy()
+    bad_ix[3] = n  # column out of range
+    short_ip = ip.copy()
+    short_ip[-1] -= 1  # row_ptr[n] != nnz
+    for a, b in ((bad_ip, ix), (ip, bad_ix), (short_ip, ix)):
+        with pytest.raises(nn.NNError) as e:
+            _solve(a, b, v, B)
+        assert e.value.status == nn.NN_ERR_ARG
+    with pytest.raises(nn.NNError):
+        _solve(ip, ix, v, B, x0="transpose")
+
+
+def test_full_size_laplacian_2048sq_closed_form():
+    nx = ny = 2048
+    shift = 0.5
+    n, nrhs = nx * ny, 16
+    _say(f"sparse laplacian {nx}x{ny} nrhs={nrhs}")
+    ip, ix, v = W.laplacian_2d(nx, ny, shift)
+    i, j = np.divmod(np.arange(n), ny)
+    pq = [(1, 1), (2, 1), (1, 3), (5, 7), (40, 3), (100, 200), (512, 512), (1000, 17),
+          (2048, 2048), (2047, 1), (3, 2040), (700, 1400), (1500, 900), (64, 64), (9, 1999),
+          (1234, 321)]
+    B = np.empty((n, nrhs))
+    lam = np.empty(nrhs)
+    for c, (p, q) in enumerate(pq):
+        B[:, c] = np.sin(np.pi * p * (i + 1) / (nx + 1)) * np.sin(np.pi * q * (j + 1) / (ny + 1))
+        lam[c] = 4 + shift - 2 * np.cos(np.pi * p / (nx + 1)) - 2 * np.cos(np.pi * q / (ny + 1))
+    ipd, ixd, vd, Bd = _dev(ip), _dev(ix), _dev(v), _dev(B)
+    th = 1.0 / (4 + shift)  # Jacobi: constant diagonal
+    T = 60
+    X, info = nn.solve_sparse(ipd, ixd, vd, Bd, x0="jacobi", fixed_terms=T)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK and info["iters"] == T
+    f = (1.0 - (1.0 - th * lam) ** (T + 1)) / lam
+    assert _relF(X.cpu().numpy(), B * f[None, :]) < 1e-10
+    X, info = nn.solve_sparse(ipd, ixd, vd, Bd, x0="jacobi", tol=1e-10, check_every=64)
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK and info["rms"] < 1e-10
+    kappa = (8 + shift) / shift
+    assert _relF(X.cpu().numpy(), B / lam[None, :]) <= kappa * info["rel_residual"] * 1.01
