@@ -1,7 +1,7 @@
 """Benchmark of the NN inversion on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--no-extras | --legs fp32,factorized,cns,starts,batched,mixed,serving]
+                    [--no-extras | --legs fp32,factorized,cns,starts,sparse,batched,mixed,serving]
 
 A step is one whole inversion through the C ABI: start-iterate prologue, then
 nests of d + 1 GEMMs until rms = ||I - A X||_F / sqrt(N) < tol.  The headline
@@ -26,7 +26,9 @@ GEMM source), the oracle timed on the host on a bounded sample, and under
   cns      the same system by the Chebyshev-Neumann series (plain and mixed
            nests for the preconditioner), against nn_solve;
   starts   the other start iterates (Frobenius and power-iteration scales,
-           Jacobi on a massive-MIMO Gram matrix) against the default ones.
+           Jacobi on a massive-MIMO Gram matrix) against the default ones;
+  sparse   a 2048 x 2048 Laplacian (CSR) by the sparse series, per-term HBM
+           roofline.
 """
 import argparse
 import json
@@ -55,7 +57,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp32,factorized,cns,starts,batched,mixed,serving",
+    ap.add_argument("--legs", default="fp32,factorized,cns,starts,sparse,batched,mixed,serving",
                     help="comma list of extra workloads to run")
     ap.add_argument("--mixed-n", type=int, default=16384)
     ap.add_argument("--serve-pool", type=int, default=64)
@@ -369,6 +371,46 @@ def leg_starts(nn, torch, workloads, np, A, n):
     return out
 
 
+def leg_sparse(nn, torch, workloads, np, grid=2048, nrhs=16, shift=0.5):
+    """W X = B for the 5-point Laplacian on a grid x grid mesh + shift I
+    (CSR, FP64; cond (8 + shift) / shift) and nrhs right-hand sides N(0,1)
+    by the sparse series (Algorithm 2, Horner form on the device) with the
+    Jacobi start, to control residual 1e-10.  The per-term time is the
+    difference of two fixed-term runs; its bytes are the algorithmic ones:
+    the CSR arrays, phi and its weights, x and B read once, x' written."""
+    ip, ix, v = workloads.laplacian_2d(grid, grid, shift)
+    n = grid * grid
+    nnz = int(ix.size)
+    B = workloads.rng(12).standard_normal((n, nrhs))
+    ipd, ixd, vd = (torch.from_numpy(a).cuda() for a in (ip, ix, v))
+    Bd = torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+
+    def timed(**kw):
+        nn.solve_sparse(ipd, ixd, vd, Bd, x0="jacobi", **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = nn.solve_sparse(ipd, ixd, vd, Bd, x0="jacobi", **kw)
+        torch.cuda.synchronize()
+        return X, info, time.perf_counter() - t0
+
+    X, info, t = timed(tol=1e-10, check_every=64)
+    _, i1, t1 = timed(fixed_terms=50)
+    _, i2, t2 = timed(fixed_terms=550)
+    per_term = (i2["device_ms"] - i1["device_ms"]) / 500.0 / 1e3
+    bytes_term = nnz * (8 + 4) + (n + 1) * 4 + 2 * n * 8 + 3 * n * nrhs * 8
+    achieved = bytes_term / per_term / 1e9
+    out = {"s": t, "solves_per_s": 1.0 / t, "status": info["status"], "terms": info["iters"],
+           "control_residual": info["rms"], "rel_residual": info["rel_residual"],
+           "per_term_ms": per_term * 1e3, "algorithmic_bytes_per_term": bytes_term,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                        "frac": achieved / 8000.0},
+           "workload": (f"5-point Laplacian {grid}x{grid} + {shift} I (n={n}, nnz={nnz}), FP64, "
+                        f"{nrhs} right-hand sides N(0,1) seed 12, Jacobi start, tol 1e-10")}
+    log(f"sparse leg: {out}")
+    return out
+
+
 def leg_serving(nn, torch, workloads, np, pool_size, n_req):
     """Poisson request stream over a pool of FP32 SPD / complex64 HPD
     matrices, N log-uniform in [32, 4096], cond log-uniform in [10, 1e4],
@@ -535,6 +577,9 @@ def main():
         extra["factorized"] = leg_factorized(nn, torch, workloads, np, A, n)
     if "cns" in legs:
         extra["cns"] = leg_cns(nn, torch, workloads, np, A, n)
+        torch.cuda.empty_cache()
+    if "sparse" in legs:
+        extra["sparse"] = leg_sparse(nn, torch, workloads, np)
         torch.cuda.empty_cache()
     if "starts" in legs:
         extra["starts"] = leg_starts(nn, torch, workloads, np, A, n)
