@@ -216,25 +216,30 @@ def leg_batched(nn, torch, workloads, np):
 
 
 def leg_mixed(nn, torch, workloads, np, n):
-    """Dense SPD N=16384, cond 1e4 (log-uniform spectrum), depth 2, scaled
-    identity start, tol 1e-11: mixed BF16/FP32/FP64 schedule vs plain FP64."""
+    """Dense SPD N=16384, cond 1e4 (log-uniform spectrum), depth 2, tol 1e-11:
+    mixed BF16/FP32/FP64 schedule vs plain FP64, each from the scaled
+    identity start I / Tr A and from Theta_2(8) I."""
     A_h, lam, Q = workloads.dense_spd(n, 1.0, 1e4, 4, log_spectrum=True, device="cuda",
                                       return_factors=True)
     A = torch.from_numpy(A_h).cuda()
     torch.cuda.synchronize()
     res = {}
     Xs = {}
-    for label, kw in (("mixed", dict(prec="mixed")), ("plain_fp64", dict(prec="plain"))):
-        X, info = nn.invert(A, depth=2, x0="identity", tol=1e-11, max_iter=100, **kw)
+    runs = (("mixed", dict(prec="mixed", x0="identity")),
+            ("plain_fp64", dict(prec="plain", x0="identity")),
+            ("mixed_power_identity", dict(prec="mixed", x0="power_identity")),
+            ("plain_fp64_power_identity", dict(prec="plain", x0="power_identity")))
+    for label, kw in runs:
+        X, info = nn.invert(A, depth=2, tol=1e-11, max_iter=100, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X, info = nn.invert(A, depth=2, x0="identity", tol=1e-11, max_iter=100, X=X, **kw)
+        X, info = nn.invert(A, depth=2, tol=1e-11, max_iter=100, X=X, **kw)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         Xs[label] = X
         ph = info["phase_iters"]
         flop = 2.0 * n ** 3 * info["gemms"]
-        if label == "mixed":
+        if label.startswith("mixed"):
             # each phase's products against its own peak; the rest of the
             # products (switch residuals, the final residual) against FP64
             per = 2.0 * n ** 3
@@ -255,10 +260,17 @@ def leg_mixed(nn, torch, workloads, np, n):
     cols = list(np.random.default_rng(1).choice(n, 4, replace=False))
     err, resid = sampled_check(A_h, X_h, lam, Q, cols)
     res["speedup_vs_plain_fp64"] = res["plain_fp64"]["s"] / res["mixed"]["s"]
+    res["speedup_power_identity_vs_plain_fp64_same_start"] = (
+        res["plain_fp64_power_identity"]["s"] / res["mixed_power_identity"]["s"])
+    res["speedup_mixed_power_identity_vs_plain_fp64_identity"] = (
+        res["plain_fp64"]["s"] / res["mixed_power_identity"]["s"])
+    res["rel_fro_diff_mixed_power_identity_vs_plain_fp64"] = (
+        torch.linalg.norm(Xs["mixed_power_identity"] - Xs["plain_fp64"]) /
+        torch.linalg.norm(Xs["plain_fp64"])).item()
     res["rel_fro_diff_mixed_vs_plain_fp64"] = diff
     res["mixed_sampled_rel_err_vs_exact_inverse_col"] = err
     res["workload"] = (f"dense SPD N={n}, spectrum log-uniform [1,1e4] (cond 1e4), depth 2, "
-                       "scaled identity start, tol rms 1e-11, seed 4")
+                       "scaled identity start (and Theta_2(8) I), tol rms 1e-11, seed 4")
     return res
 
 
@@ -432,8 +444,8 @@ def leg_serving(nn, torch, workloads, np, pool_size, n_req):
         f = (rec["iters"] * (d + 1) + 1) * 2.0 * rec["n"] ** 3
         return f * (4 if pool[picks[rec["id"]]]["complex"] else 1)
 
-    def run(rate):
-        srv = nn.Server(96 << 30, depth=d, max_active=512, n_streams=4)
+    def run(rate, x0="power_identity"):
+        srv = nn.Server(96 << 30, depth=d, x0=x0, max_active=512, n_streams=4)
         srv.submit(-1, mats[0], 1e-4)
         srv.run_until_idle()
         srv.release(-1)
@@ -469,27 +481,33 @@ def leg_serving(nn, torch, workloads, np, pool_size, n_req):
 
     out = {"capacity_closed_loop": run(None)}
     log(f"serving capacity: {out['capacity_closed_loop']}")
+    out["capacity_identity_start"] = run(None, "identity")
+    log(f"serving capacity, I / Tr A start: {out['capacity_identity_start']}")
     out["open_loop_2000"] = run(2000.0)
     log(f"serving 2000 req/s: {out['open_loop_2000']}")
     half = 0.5 * out["capacity_closed_loop"]["inverses_per_s"]
     out["open_loop_half_capacity"] = run(half)
     log(f"serving {half:.0f} req/s: {out['open_loop_half_capacity']}")
-    # the same requests one by one through plain FP64 nn_invert
+    # the same requests one by one through plain FP64 nn_invert, same start
     wide = {}
     for i in set(int(x) for x in picks):
         wide[i] = mats[i].to(torch.complex128 if mats[i].is_complex() else torch.float64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r, i in enumerate(picks):
-        nn.invert(wide[int(i)], depth=d, x0="identity", tol=tols[r], max_iter=100)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    out["plain_fp64_sequential"] = {"wall_s": t, "inverses_per_s": n_req / t}
-    out["served_vs_plain_fp64"] = out["capacity_closed_loop"]["inverses_per_s"] / (n_req / t)
+    for x0 in ("power_identity", "identity"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, i in enumerate(picks):
+            nn.invert(wide[int(i)], depth=d, x0=x0, tol=tols[r], max_iter=100)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        key = "plain_fp64_sequential" + ("" if x0 == "power_identity" else "_identity_start")
+        out[key] = {"wall_s": t, "inverses_per_s": n_req / t}
+        log(f"serving {key}: {out[key]}")
+    out["served_vs_plain_fp64"] = (out["capacity_closed_loop"]["inverses_per_s"] /
+                                   out["plain_fp64_sequential"]["inverses_per_s"])
     out["workload"] = (f"{n_req} requests drawn from a pool of {pool_size} (seed 5): FP32 SPD or "
                        "complex64 HPD 50/50, N log-uniform [32,4096], cond log-uniform [10,1e4], "
-                       "tol 1e-4 or 1e-8 50/50; depth 2, scaled identity start; latency = "
-                       "arrival to result in host memory")
+                       "tol 1e-4 or 1e-8 50/50; depth 2, Theta_2(8) I start (I / Tr A for the "
+                       "*_identity_start entries); latency = arrival to result in host memory")
     return out
 
 

@@ -89,7 +89,9 @@ typedef enum {
 typedef enum {
   NN_PREC_PLAIN = 0, /* every GEMM in the dtype of A */
   /* NN_F64 only: bulk nests as BF16 MFMA GEMMs with FP32 accumulation, then
-     FP32, then FP64 residual and refinement nests; X and rms in FP64. */
+     FP32, then FP64 residual and refinement nests; X and rms in FP64.
+     Tolerance mode with NN_X0_SCALED_IDENTITY or NN_X0_POWER_IDENTITY
+     (Hermitian PD A). */
   NN_PREC_MIXED = 1
 } nn_prec;
 
@@ -409,10 +411,13 @@ typedef struct nn_server nn_server;
 
 typedef struct {
   int32_t depth;      /* inception depth d, 1 <= d <= NN_MAX_DEPTH */
-  int32_t x0;         /* NN_X0_SCALED_IDENTITY (HPD requests) or NN_X0_TRANSPOSE */
+  int32_t x0;         /* any nn_x0 but NN_X0_GIVEN (the identity-family and
+                         Jacobi starts for HPD requests) */
   int32_t max_active; /* requests on the device at once, 1..65536 */
   int32_t n_streams;  /* streams the requests are spread over, 1..8 */
   double wide_tol;    /* tolerances below this finish in FP64 / complex128 */
+  int32_t power_k;    /* NN_X0_POWER_*: power steps, 1..NN_POWER_MAX_K */
+  int32_t reserved;   /* ignored; set to 0 */
 } nn_server_params;
 
 typedef struct {
@@ -440,7 +445,7 @@ typedef struct {
 /* Create a server on ctx's device.  `pool` is a device buffer of pool_bytes
  * (256-byte aligned) owned by the caller and used by the server until
  * nn_server_destroy; params NULL selects {2, NN_X0_SCALED_IDENTITY, 1024, 4,
- * 1e-6}. */
+ * 1e-6, 8, 0}. */
 nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
                            const nn_server_params* params, nn_server** server);
 

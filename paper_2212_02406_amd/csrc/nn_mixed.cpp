@@ -5,8 +5,8 @@
 // with ||I - A X||_2 < 1 is a valid start, Appendix 2):
 //
 //   B  BF16 products with FP32 accumulation, FP32 master iterate.  The
-//      start is the paper's own X_0 = I / Tr(A) (Sec. II-A, Sec. II-D), whose
-//      iterate norm stays small for many nests.  BF16 rounding perturbs A X by
+//      start is the paper's own X_0 = I / Tr(A) (Sec. II-A, Sec. II-D), or
+//      Theta_2(k) I, whose iterate norm stays small for many nests.  BF16 rounding perturbs A X by
 //      about u_bf16 ||A|| ||X||; the phase ends while that is still small:
 //      when u_bf16 ||A||_F ||X||_F / N > 0.1, or when the rms stops decreasing.
 //   F  FP32 products and residual, until two FP64 nests will reach the
@@ -56,6 +56,8 @@ struct MixedWs {
   double* part;
   double* scal;   // [0] den, [1] ||A||_F, [2] rms, [3] ||X||_F
   double* spart;  // sum-of-squares partials
+  double* denpart;  // start-iterate scratch (power steps)
+  double* pw;
   size_t bytes;
   int64_t ldb;    // leading dimension of the BF16 buffers
 };
@@ -94,6 +96,8 @@ MixedWs carve(void* base, int64_t n, int depth) {
   const int tiles = std::max({p64.num_tiles(), p32.num_tiles(), pb.num_tiles(), 1});
   w.part = static_cast<double*>(take(sizeof(double) * tiles));
   w.spart = static_cast<double*>(take(sizeof(double) * 256));
+  w.denpart = static_cast<double*>(take(sizeof(double) * den_partials_elems(n)));
+  w.pw = static_cast<double*>(take(sizeof(double) * start_scratch_doubles(n)));
   w.scal = static_cast<double*>(take(sizeof(double) * 16));
   w.bytes = off;
   return w;
@@ -153,7 +157,9 @@ size_t mixed_workspace_size(int64_t n, const nn_params* prm) {
 nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t ldx, int64_t n,
                     const nn_params* prm, void* ws, size_t ws_bytes, nn_info* info) {
   (void)ws_bytes;
-  if (prm->x0 != NN_X0_SCALED_IDENTITY || prm->fixed_iter != 0) return NN_ERR_UNSUPPORTED;
+  if ((prm->x0 != NN_X0_SCALED_IDENTITY && prm->x0 != NN_X0_POWER_IDENTITY) ||
+      prm->fixed_iter != 0)
+    return NN_ERR_UNSUPPORTED;
   const double* A = static_cast<const double*>(Av);
   double* X = static_cast<double*>(Xv);
   const MixedWs w = carve(ws, n, prm->depth);
@@ -167,8 +173,13 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
   int iters = 0;
 
   HIP_TRY(hipEventRecord(ctx->ev_start, s));
-  // Start: den = Tr A (FP64), X_0 = I / den in FP32; copies of A in FP32 and BF16.
-  HIP_TRY(launch_den_trace(NN_F64, A, lda, n, w.scal, s));
+  // Start: den = Tr A or 1 / Theta_2(k) of A (FP64; the caller's X serves as
+  // the scratch FP64 start), X_0 = I / den in FP32; copies of A in FP32, BF16.
+  if (prm->x0 == NN_X0_POWER_IDENTITY)
+    HIP_TRY(launch_start(NN_F64, NN_X0_POWER_IDENTITY, prm->power_k, A, lda, X, ldx, n, w.denpart,
+                         w.pw, w.scal, s));
+  else
+    HIP_TRY(launch_den_trace(NN_F64, A, lda, n, w.scal, s));
   HIP_TRY(launch_sumsq(A, true, lda, n, n, w.spart, w.scal + 1, s));
   HIP_TRY(r.fetch(w.scal, 2));
   const double den = ctx->host[0], normA = ctx->host[1];

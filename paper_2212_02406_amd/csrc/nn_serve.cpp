@@ -124,6 +124,7 @@ struct Request {
   int cur_ph = 0;
   double* part = nullptr;     // residual GEMM tile partials
   double* denpart = nullptr;  // norm partials of the transpose start
+  double* pw = nullptr;       // power-step scratch of the Theta_2 starts
   double* scal = nullptr;     // [0] den
   int slot = -1;
   int stream = 0;
@@ -146,13 +147,14 @@ Elem elem_of(nn_dtype d) { return is_double(d) ? Elem::F64 : Elem::F32; }
 size_t mats_per_phase(int depth) { return 4 + (depth >= 2) + (depth >= 3); }
 
 // Bytes of the per-request control region: tile partials (enough for either
-// precision's plan), norm partials, scalars.
+// precision's plan), norm partials, power-step scratch, scalars.
 size_t control_bytes(int64_t n, nn_dtype dt) {
   const int cm = is_complex(dt) ? 2 : 1;
   const int t64 = plan_gemm(Elem::F64, n, cm * n).num_tiles();
   const int t32 = plan_gemm(Elem::F32, n, cm * n).num_tiles();
   return up(sizeof(double) * (size_t)std::max({t64, t32, 1})) +
-         up(sizeof(double) * den_partials_elems(n)) + up(sizeof(double) * 8);
+         up(sizeof(double) * den_partials_elems(n)) +
+         up(sizeof(double) * start_scratch_doubles(n)) + up(sizeof(double) * 8);
 }
 
 size_t phase_bytes(int64_t n, nn_dtype dt, int depth) {
@@ -232,6 +234,8 @@ void carve_request(nn_server* s, Request* q) {
   b += up(sizeof(double) * (size_t)std::max({t64, t32, 1}));
   q->denpart = reinterpret_cast<double*>(b);
   b += up(sizeof(double) * den_partials_elems(q->n));
+  q->pw = reinterpret_cast<double*>(b);
+  b += up(sizeof(double) * start_scratch_doubles(q->n));
   q->scal = reinterpret_cast<double*>(b);
   b += up(sizeof(double) * 8);
   const int d = s->prm.depth;
@@ -288,13 +292,8 @@ hipError_t enqueue_start(nn_server* s, Request* q) {
   hipError_t err = hipMemcpy2DAsync(P.A, (size_t)q->n * e, q->src, (size_t)q->src_ld * e,
                                     (size_t)q->n * e, (size_t)q->n, hipMemcpyDefault, st);
   if (err != hipSuccess) return err;
-  if (s->prm.x0 == NN_X0_TRANSPOSE) {
-    err = launch_den_transpose(q->dt, P.A, q->n, q->n, q->denpart, q->scal, st);
-    if (err == hipSuccess) err = launch_x0_transpose(q->dt, P.A, q->n, P.X[0], q->n, q->n, q->scal, st);
-  } else {
-    err = launch_den_trace(q->dt, P.A, q->n, q->n, q->scal, st);
-    if (err == hipSuccess) err = launch_x0_identity(q->dt, P.X[0], q->n, q->n, q->scal, st);
-  }
+  err = launch_start(q->dt, s->prm.x0, s->prm.power_k, P.A, q->n, P.X[0], q->n, q->n, q->denpart,
+                     q->pw, q->scal, st);
   if (err != hipSuccess) return err;
   err = hipMemcpyAsync(s->slots_dev + 2 * q->slot + 1, q->scal, sizeof(double),
                        hipMemcpyDeviceToDevice, st);
@@ -487,10 +486,13 @@ extern "C" {
 nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
                            const nn_server_params* params, nn_server** out) {
   if (!ctx || !pool || !out) return NN_ERR_ARG;
-  nn_server_params p{2, NN_X0_SCALED_IDENTITY, 1024, 4, 1e-6};
+  nn_server_params p{2, NN_X0_SCALED_IDENTITY, 1024, 4, 1e-6, 8, 0};
   if (params) p = *params;
   if (p.depth < 1 || p.depth > NN_MAX_DEPTH) return NN_ERR_ARG;
-  if (p.x0 != NN_X0_SCALED_IDENTITY && p.x0 != NN_X0_TRANSPOSE) return NN_ERR_ARG;
+  if (p.x0 < NN_X0_TRANSPOSE || p.x0 > NN_X0_JACOBI || p.x0 == NN_X0_GIVEN) return NN_ERR_ARG;
+  if ((p.x0 == NN_X0_POWER_IDENTITY || p.x0 == NN_X0_POWER_TRANSPOSE) &&
+      (p.power_k < 1 || p.power_k > NN_POWER_MAX_K))
+    return NN_ERR_ARG;
   if (p.max_active < 1 || p.max_active > kMaxActiveLimit) return NN_ERR_ARG;
   if (p.n_streams < 1 || p.n_streams > kMaxStreams) return NN_ERR_ARG;
   if (!(p.wide_tol >= 0.0)) return NN_ERR_ARG;

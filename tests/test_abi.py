@@ -33,7 +33,7 @@ def test_struct_layout():
     assert nn.nn_info.rms_trace.offset == 48
     assert ctypes.sizeof(nn.nn_info) == 48 + 8 * nn.NN_TRACE_MAX
     assert ctypes.sizeof(nn.nn_info_dev) == 16
-    assert ctypes.sizeof(nn.nn_server_params) == 24
+    assert ctypes.sizeof(nn.nn_server_params) == 32 and nn.nn_server_params.power_k.offset == 24
     assert ctypes.sizeof(nn.nn_request_info) == 64
     assert nn.nn_request_info.rms.offset == 32
     assert ctypes.sizeof(nn.nn_server_stats) == 24

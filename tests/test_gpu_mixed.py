@@ -96,3 +96,21 @@ def test_mixed_loose_tolerance_ends_in_fp32(n, tol):
     # perturbation: the oracle's rms after the same number of nests is close
     _, io = oracle.nn_ref(A, d=2, x0=oracle.X0_SCALED_IDENTITY, fixed_iter=info["iters"])
     assert rms <= 4.0 * io["rms"] + 1e-6
+
+
+@pytest.mark.parametrize("n,cond", [(512, 1e4), (1000, 1e3)])
+def test_mixed_power_identity_start(n, cond):
+    """The mixed schedule from Theta_2(8) I: against the oracle's converged
+    FP64 iterate from the same start (1e-10), in fewer nests than I / Tr A."""
+    _say(f"mixed power_identity n={n} cond={cond:g}")
+    A = W.dense_spd(n, 1.0, cond, 70 + n, log_spectrum=True)
+    At = torch.from_numpy(A).to(DEV)
+    Xo, io = oracle.nn_ref(A, d=2, x0=oracle.X0_POWER_IDENTITY, tol=1e-12, max_iter=200, power_k=8)
+    X, info = nn.invert(At, depth=2, x0="power_identity", tol=1e-12, max_iter=200, prec="mixed",
+                        power_k=8)
+    _, i1 = nn.invert(At, depth=2, x0="identity", tol=1e-12, max_iter=200, prec="mixed")
+    torch.cuda.synchronize()
+    assert io["status"] == oracle.OK and info["status"] == nn.NN_OK, info
+    assert info["rms"] < 1e-12
+    assert np.linalg.norm(X.cpu().numpy() - Xo) / np.linalg.norm(Xo) < 1e-10
+    assert info["iters"] <= i1["iters"]

@@ -105,14 +105,20 @@ CASES = [(32, 10.0, False), (100, 100.0, True), (257, 1e3, False), (384, 50.0, T
          (512, 1e3, True), (129, 1e3, False)]
 
 
-def test_single_precision_results_equal_nn_invert():
-    _say("serve narrow == nn_invert")
-    reqs = [(i, _mat(n, c, 100 + i, cx), 1e-4, 100) for i, (n, c, cx) in enumerate(CASES)]
-    res = _serve(reqs)
+@pytest.mark.parametrize("x0", ["identity", "power_identity", "jacobi"])
+def test_single_precision_results_equal_nn_invert(x0):
+    _say(f"serve narrow == nn_invert x0={x0}")
+    if x0 == "jacobi":  # a start that needs diagonal dominance: MIMO-like Gram matrices
+        reqs = [(i, W.mimo_gram(8 * n, n, 150 + i, complex_=cx,
+                                dtype=np.complex64 if cx else np.float32), 1e-4, 100)
+                for i, (n, _, cx) in enumerate(CASES)]
+    else:
+        reqs = [(i, _mat(n, c, 100 + i, cx), 1e-4, 100) for i, (n, c, cx) in enumerate(CASES)]
+    res = _serve(reqs, x0=x0)
     for rid, A, tol, _ in reqs:
         rec, X = res[rid]
         assert rec["status"] == nn.NN_OK and rec["wide_iters"] == 0, rec
-        Xi, info = nn.invert(_dev(A), depth=2, x0="identity", tol=tol, max_iter=100)
+        Xi, info = nn.invert(_dev(A), depth=2, x0=x0, tol=tol, max_iter=100)
         torch.cuda.synchronize()
         assert info["status"] == nn.NN_OK and info["iters"] == rec["iters"], (info, rec)
         assert info["rms"] == rec["rms"]
