@@ -395,10 +395,11 @@ size_t nn_solve_workspace_size(int64_t n, int64_t nrhs, nn_dtype dt, const nn_pa
   const size_t inv = up((size_t)n * n * esz);
   const size_t rb = up((size_t)n * nrhs * esz);
   const int cm = is_complex(dt) ? 2 : 1;
-  const GemmPlan plan =
-      plan_gemm(is_double(dt) ? Elem::F64 : Elem::F32, n, (int64_t)cm * nrhs);
+  const Elem el = is_double(dt) ? Elem::F64 : Elem::F32;
+  const GemmPlan plan = plan_gemm_k(el, n, (int64_t)cm * nrhs, (int64_t)cm * n);
   const size_t part = up(sizeof(double) * std::max(plan.num_tiles(), 256)) + up(sizeof(double) * 8);
-  return inv + rb + part + carve_plain(nullptr, n, dt, prm->depth).bytes;
+  return inv + rb + part + up(gemm_work_bytes(plan, el, n, (int64_t)cm * nrhs)) +
+         carve_plain(nullptr, n, dt, prm->depth).bytes;
 }
 
 nn_status nn_solve(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
@@ -420,9 +421,11 @@ nn_status nn_solve(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64
   void* Rb = c.take((size_t)n * nrhs * esz);
   const int cm = is_complex(dt) ? 2 : 1;
   const Elem e = is_double(dt) ? Elem::F64 : Elem::F32;
-  const GemmPlan plan = plan_gemm(e, n, (int64_t)cm * nrhs);
+  const GemmPlan plan = plan_gemm_k(e, n, (int64_t)cm * nrhs, (int64_t)cm * n);
   double* part = static_cast<double*>(c.take(sizeof(double) * std::max(plan.num_tiles(), 256)));
   double* scal = static_cast<double*>(c.take(sizeof(double) * 8));
+  const size_t wb = gemm_work_bytes(plan, e, n, (int64_t)cm * nrhs);
+  void* work = wb ? c.take(wb) : nullptr;
   void* rest = c.base + c.off;
   const PlainWs w = carve_plain(rest, n, dt, prm->depth);
   nn_info local;
@@ -434,11 +437,13 @@ nn_status nn_solve(nn_ctx* ctx, const void* A, int64_t lda, const void* B, int64
   // Xsol = Xinv B  (n x n times n x nrhs).
   GemmArgs g{Xinv, (int64_t)cm * n, B, (int64_t)cm * ldb, Xsol, (int64_t)cm * ldx, nullptr, 0, n,
              (int64_t)cm * nrhs, (int64_t)cm * n, 1.0, 0.0, nullptr};
+  g.work = work;
   HIP_TRY(launch_gemm(e, cplx, plan, g, s));
   if (rel_residual) {
     // Rb = B - A Xsol with partials -> ||Rb||_F; ||B||_F by a plain sum of squares.
     GemmArgs r{A, (int64_t)cm * lda, Xsol, (int64_t)cm * ldx, Rb, (int64_t)cm * nrhs, B,
                (int64_t)cm * ldb, n, (int64_t)cm * nrhs, (int64_t)cm * n, -1.0, 0.0, part};
+    r.work = work;
     HIP_TRY(launch_gemm(e, cplx, plan, r, s));
     HIP_TRY(launch_rms_reduce(part, plan.num_tiles(), 1, scal, s));
     HIP_TRY(launch_sumsq(B, is_double(dt), (int64_t)cm * ldb, n, (int64_t)cm * nrhs, part,

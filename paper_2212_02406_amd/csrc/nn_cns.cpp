@@ -43,6 +43,7 @@ struct CnsWs {
   double* part = nullptr;   // per-tile partials
   double* scal = nullptr;   // [0] ||B||_F
   double* stats = nullptr;  // ||B - A y_k||_F per term
+  void* work = nullptr;     // split-K partials of the thin products
   size_t bytes = 0;
 };
 
@@ -75,10 +76,13 @@ CnsWs carve(void* base, int64_t n, int64_t nrhs, nn_dtype dt, const nn_params* p
   w.inv_ws = take(w.inv_bytes);
   w.yalt = take((size_t)n * nrhs * e);
   w.r = take((size_t)n * nrhs * e);
-  const int tiles = std::max({plan_gemm(el, n, cm * nrhs).num_tiles(), kSumsqParts, 1});
+  const GemmPlan pnr = plan_gemm_k(el, n, cm * nrhs, cm * n);
+  const int tiles = std::max({pnr.num_tiles(), kSumsqParts, 1});
   w.part = static_cast<double*>(take(sizeof(double) * (size_t)tiles));
   w.scal = static_cast<double*>(take(sizeof(double) * 8));
   w.stats = static_cast<double*>(take(sizeof(double) * kStats));
+  const size_t wb = gemm_work_bytes(pnr, el, n, cm * nrhs);
+  w.work = wb ? take(wb) : nullptr;
   w.bytes = off;
   return w;
 }
@@ -149,7 +153,7 @@ nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, i
   const Elem e = is_double(dt) ? Elem::F64 : Elem::F32;
   const int64_t cm = cplx ? 2 : 1;
   const int64_t nr = cm * n, rr = cm * nrhs;  // real extents
-  const GemmPlan pnr = plan_gemm(e, n, rr);
+  const GemmPlan pnr = plan_gemm_k(e, n, rr, nr);
   const size_t esz = elem_size(dt);
   int gemms = 0;
   double trace[NN_TRACE_MAX];
@@ -176,6 +180,7 @@ nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, i
   // y_0 = phi B (in Xsol)
   {
     GemmArgs g{w.phi, nr, B, cm * ldb, Xsol, cm * ldx, nullptr, 0, n, rr, nr, 1.0, 0.0, nullptr};
+    g.work = w.work;
     HIP_TRY(launch_gemm(e, cplx, pnr, g, s));
     ++gemms;
   }
@@ -197,6 +202,7 @@ nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, i
     // r = B - A y_k, ||r||_F into stats[k]
     GemmArgs r{A, cm * lda, cur, cm * ld_cur, w.r, rr, B, cm * ldb, n, rr, nr, -1.0, 0.0,
                w.part};
+    r.work = w.work;
     HIP_TRY(launch_gemm(e, cplx, pnr, r, s));
     ++gemms;
     HIP_TRY(launch_rms_reduce(w.part, pnr.num_tiles(), 1, w.stats + std::min(k, kStats - 1), s));
@@ -229,6 +235,7 @@ nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, i
     // y_{k+1} = y_k + phi r
     GemmArgs u{w.phi, nr, w.r, rr, alt, cm * ld_alt, cur, cm * ld_cur, n, rr, nr, 1.0, 0.0,
                nullptr};
+    u.work = w.work;
     HIP_TRY(launch_gemm(e, cplx, pnr, u, s));
     ++gemms;
     std::swap(cur, alt);

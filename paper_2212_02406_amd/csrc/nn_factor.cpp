@@ -42,6 +42,7 @@ struct FactorWs {
   double* pw = nullptr;     // start-iterate scratch
   double* scal = nullptr;   // [0] den, [1] ||B||_F
   double* stats = nullptr;  // ||B - A y_s||_F per s
+  void* work = nullptr;     // split-K partials of the thin products
   size_t bytes = 0;
 };
 
@@ -62,12 +63,15 @@ FactorWs carve(void* base, int64_t n, int64_t nrhs, nn_dtype dt) {
   w.p[1] = take((size_t)n * n * e);
   w.yalt = take((size_t)n * nrhs * e);
   w.r = take((size_t)n * nrhs * e);
-  const int tiles = std::max({plan_gemm(el, n, cm * nrhs).num_tiles(), kSumsqParts, 1});
+  const GemmPlan pnr = plan_gemm_k(el, n, cm * nrhs, cm * n);
+  const int tiles = std::max({pnr.num_tiles(), kSumsqParts, 1});
   w.part = static_cast<double*>(take(sizeof(double) * (size_t)tiles));
   w.denpart = static_cast<double*>(take(sizeof(double) * den_partials_elems(n)));
   w.pw = static_cast<double*>(take(sizeof(double) * start_scratch_doubles(n)));
   w.scal = static_cast<double*>(take(sizeof(double) * 8));
   w.stats = static_cast<double*>(take(sizeof(double) * kStats));
+  const size_t wb = gemm_work_bytes(pnr, el, n, cm * nrhs);
+  w.work = wb ? take(wb) : nullptr;
   w.bytes = off;
   return w;
 }
@@ -129,7 +133,7 @@ nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const voi
   const Elem e = is_double(dt) ? Elem::F64 : Elem::F32;
   const int64_t cm = cplx ? 2 : 1;
   const int64_t nr = cm * n, rr = cm * nrhs;  // real extents
-  const GemmPlan pnn = plan_gemm(e, n, nr), pnr = plan_gemm(e, n, rr);
+  const GemmPlan pnn = plan_gemm(e, n, nr), pnr = plan_gemm_k(e, n, rr, nr);
   const size_t esz = elem_size(dt);
   int gemms = 0;
   double trace[NN_TRACE_MAX];
@@ -168,6 +172,7 @@ nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const voi
     GemmArgs g{w.phi, nr, A, cm * lda, w.p[0], nr, nullptr, 0, n, nr, nr, -1.0, 1.0, nullptr};
     HIP_TRY(launch_gemm(e, cplx, pnn, g, s));
     GemmArgs h{w.phi, nr, B, cm * ldb, Xsol, cm * ldx, nullptr, 0, n, rr, nr, 1.0, 0.0, nullptr};
+    h.work = w.work;
     HIP_TRY(launch_gemm(e, cplx, pnr, h, s));
     gemms += 2;
   }
@@ -186,6 +191,7 @@ nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const voi
     // residual of y_k: R = B - A y_k, ||R||_F into stats[k]
     GemmArgs r{A, cm * lda, cur, cm * ld_cur, w.r, rr, B, cm * ldb, n, rr, nr, -1.0, 0.0,
                w.part};
+    r.work = w.work;
     HIP_TRY(launch_gemm(e, cplx, pnr, r, s));
     ++gemms;
     HIP_TRY(launch_rms_reduce(w.part, pnr.num_tiles(), 1, w.stats + std::min(k, kStats - 1), s));
@@ -226,6 +232,7 @@ nn_status nn_solve_factorized(nn_ctx* ctx, const void* A, int64_t lda, const voi
     }
     GemmArgs u{w.p[pk], nr, cur, cm * ld_cur, alt, cm * ld_alt, cur, cm * ld_cur, n, rr, nr, 1.0,
                0.0, nullptr};
+    u.work = w.work;
     HIP_TRY(launch_gemm(e, cplx, pnr, u, s));
     ++gemms;
     std::swap(cur, alt);

@@ -151,9 +151,15 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   int pm, pn;
-  grouped_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, pm, pn);
+  const int ntile = tiles_m * tiles_n;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int sidx = bid / ntile;  // k split of this workgroup (0 when unsplit)
+  grouped_tile(bid - sidx * ntile, tiles_m, tiles_n, pm, pn);
   const int64_t m0 = (int64_t)pm * BM, n0 = (int64_t)pn * BN;
   const int64_t M = p.M, N = p.N, K = p.K;
+  // k range [kbeg, kend): a multiple of BK wide except at the end of K
+  const int64_t kbeg = p.kchunk ? (int64_t)sidx * p.kchunk : 0;
+  const int64_t kend = p.kchunk ? (kbeg + p.kchunk < K ? kbeg + p.kchunk : K) : K;
   const T* __restrict__ A = static_cast<const T*>(p.A);
   const T* __restrict__ B = static_cast<const T*>(p.B);
 
@@ -288,17 +294,35 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
 
   // Steady state without conditionals: prefetch slab kt+1 into registers,
   // multiply slab kt from LDS, store slab kt+1 into the other LDS buffer.
-  const int nk = (int)((K + BK - 1) / BK);
-  load(0);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  load(kbeg);
   sstore(0);
   __syncthreads();
   for (int kt = 0; kt < nk - 1; ++kt) {
-    load((int64_t)(kt + 1) * BK);
+    load(kbeg + (int64_t)(kt + 1) * BK);
     compute(kt & 1);
     sstore((kt + 1) & 1);
     __syncthreads();
   }
   compute((nk - 1) & 1);
+
+  if (p.work) {
+    // split-K: the raw partial product of this k range, row-major M x N
+    T* __restrict__ Wp = static_cast<T*>(p.work) + (int64_t)sidx * M * N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int64_t c = n0 + wn * WTN + j * 16 + lr;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t r = m0 + wm * WTM + i * 16 + Mfma<T>::row(lk, t);
+          if (EXACT || (r < M && c < N)) Wp[r * N + c] = acc[i][j][t];
+        }
+      }
+    }
+    return;
+  }
 
   // Epilogue: C = alpha * acc + E + diag * I, and the tile's sum of squares.
   T* __restrict__ C = static_cast<T*>(p.C);
@@ -337,6 +361,44 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
   }
 }
 
+// Split-K epilogue, one workgroup per output tile: C = alpha * sum_s W_s +
+// E + diag * I with the partials summed in split order, and the tile's sum
+// of squares in partials[tile] (the unsplit kernel's indexing).
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256) splitk_epilogue(GemmArgs p, int split, int bm, int bn,
+                                                       int tiles_n) {
+  __shared__ double red[256];
+  const int tile = blockIdx.x;
+  const int64_t m0 = (int64_t)(tile / tiles_n) * bm, n0 = (int64_t)(tile % tiles_n) * bn;
+  const int64_t M = p.M, N = p.N;
+  const T* __restrict__ Wp = static_cast<const T*>(p.work);
+  T* __restrict__ C = static_cast<T*>(p.C);
+  const T* __restrict__ E = static_cast<const T*>(p.E);
+  const T alpha = (T)p.alpha, diag = (T)p.diag;
+  double ss = 0.0;
+  for (int e = threadIdx.x; e < bm * bn; e += 256) {
+    const int64_t r = m0 + e / bn, c = n0 + e % bn;
+    if (r < M && c < N) {
+      T v = T(0);
+      for (int sp = 0; sp < split; ++sp) v += Wp[((int64_t)sp * M + r) * N + c];
+      v = alpha * v;
+      if (E) v += E[r * p.lde + c];
+      if (CPLX ? (c == 2 * r) : (c == r)) v += diag;
+      C[r * p.ldc + c] = v;
+      ss += (double)v * (double)v;
+    }
+  }
+  if (p.partials) {
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) p.partials[tile] = red[0];
+  }
+}
+
 struct TileShape {
   int bm, bn;
 };
@@ -357,16 +419,31 @@ inline TileShape shape_of(Tile t) {
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC, int VEC, bool CPLX>
 hipError_t launch_one(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
-  const int grid = plan.num_tiles();
-  if (grid <= 0) return hipSuccess;
+  const int ntile = plan.num_tiles();
+  if (ntile <= 0) return hipSuccess;
+  // k split: whole slabs per split and no empty split
+  GemmArgs b = a;
+  int split = 1;
+  b.kchunk = 0;
+  if (a.work && plan.split > 1) {
+    const int64_t slabs = (a.K + BK - 1) / BK;
+    const int64_t per = (slabs + plan.split - 1) / plan.split;
+    split = (int)((slabs + per - 1) / per);
+    if (split > 1) b.kchunk = per * BK;
+  }
+  if (split == 1) b.work = nullptr;
+  const int grid = ntile * split;
   // every tile interior: the kernel without bounds checks
   const bool exact = a.M % BM == 0 && a.N % BN == 0 && a.K % BK == 0;
   if (exact)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, OCC, VEC, CPLX, true>), dim3(grid),
-                       dim3(WM * WN * 64), 0, s, a, plan.tiles_m, plan.tiles_n);
+                       dim3(WM * WN * 64), 0, s, b, plan.tiles_m, plan.tiles_n);
   else
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, OCC, VEC, CPLX, false>), dim3(grid),
-                       dim3(WM * WN * 64), 0, s, a, plan.tiles_m, plan.tiles_n);
+                       dim3(WM * WN * 64), 0, s, b, plan.tiles_m, plan.tiles_n);
+  if (split > 1)
+    hipLaunchKernelGGL((splitk_epilogue<T, CPLX>), dim3(ntile), dim3(256), 0, s, a, split, BM, BN,
+                       plan.tiles_n);
   return hipGetLastError();
 }
 
@@ -421,6 +498,33 @@ GemmPlan plan_gemm(Elem e, int64_t M, int64_t N) {
   p.tiles_m = (int)((M + sh.bm - 1) / sh.bm);
   p.tiles_n = (int)((N + sh.bn - 1) / sh.bn);
   return p;
+}
+
+int slab_of(Tile t) {
+  return (t == Tile::T128K8 || t == Tile::T128W8K8 || t == Tile::T256K8) ? 8 : 16;
+}
+
+GemmPlan plan_gemm_k(Elem e, int64_t M, int64_t N, int64_t K) {
+  GemmPlan p = plan_gemm(e, M, N);
+  const int64_t slabs = (K + slab_of(p.tile) - 1) / slab_of(p.tile);
+  const char* v = getenv("NN_GEMM_SPLIT");
+  int s = 1;
+  if (v) {
+    s = atoi(v);
+    if (s < 1) s = 1;
+    while (s > 1 && s > slabs) s >>= 1;
+  } else {
+    // aim at >= 1024 workgroups, each split keeping >= 32 slabs
+    while (p.num_tiles() < 512 && (int64_t)p.num_tiles() * s * 2 <= 1024 && slabs / (s * 2) >= 32)
+      s *= 2;
+  }
+  p.split = s;
+  return p;
+}
+
+size_t gemm_work_bytes(const GemmPlan& plan, Elem e, int64_t M, int64_t N) {
+  if (plan.split <= 1) return 0;
+  return (size_t)plan.split * (size_t)M * (size_t)N * (e == Elem::F64 ? 8 : 4);
 }
 
 hipError_t launch_gemm(Elem e, bool cplx, const GemmPlan& plan, const GemmArgs& a,

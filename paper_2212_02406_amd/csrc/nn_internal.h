@@ -27,6 +27,10 @@ struct GemmArgs {
   double alpha;
   double diag;
   double* partials;  // may be null
+  // Split-K (only for plans with split > 1): a caller-provided buffer of
+  // gemm_work_bytes() for the split partial products; null runs unsplit.
+  void* work = nullptr;
+  int64_t kchunk = 0;  // set by launch_gemm: k extent of one split (0: all of K)
 };
 
 enum class Elem { F64, F32, BF16IN_F32OUT };
@@ -47,11 +51,19 @@ enum class Tile { T128, T128W8, T128K8, T128W8K8, T256K8, T256, T64, T32, kCount
 struct GemmPlan {
   Tile tile;
   int tiles_m, tiles_n;
+  int split = 1;  // k splits (plan_gemm_k only)
   int num_tiles() const { return tiles_m * tiles_n; }
 };
 
 // Plan (tile choice, grid) for a real M x N product.
 GemmPlan plan_gemm(Elem e, int64_t M, int64_t N);
+// The same plus a k split for products whose tiles cannot fill the chip
+// (thin outputs, long K): each split multiplies a K/split slab range into a
+// partial buffer, and a second kernel sums the partials in split order and
+// applies the epilogue.  NN_GEMM_SPLIT (a power of two) forces the split.
+GemmPlan plan_gemm_k(Elem e, int64_t M, int64_t N, int64_t K);
+// Bytes of the partial buffer a plan_gemm_k plan needs (0 if unsplit).
+size_t gemm_work_bytes(const GemmPlan& plan, Elem e, int64_t M, int64_t N);
 
 // Enqueue C = alpha A B + E + diag I on `stream`.  `complex_b` expands B on
 // the fly into the real 2K x 2N form of a complex matrix (A, C, E are then
