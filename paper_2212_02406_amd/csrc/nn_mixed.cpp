@@ -9,11 +9,14 @@
 //      Theta_2(k) I, whose iterate norm stays small for many nests.  BF16 rounding perturbs A X by
 //      about u_bf16 ||A|| ||X||; the phase ends while that is still small:
 //      when u_bf16 ||A||_F ||X||_F / N > 0.1, or when the rms stops decreasing.
-//   F  FP32 products and residual, until two FP64 nests will reach the
-//      tolerance (rms^((d+1)^2) < tol: each exact nest raises the residual to
-//      the power d+1, Appendix 2), or until the rms stagnates in the asymptotic
-//      regime (sqrt(N) rms_{k-1} < 0.1 and rms_k >= rms_{k-1} / 2) — the FP32
-//      rounding floor.  A loose tolerance (tol >= 1e-4, far above that floor:
+//   F  FP32 products and residual, while one more FP32 nest is predicted to
+//      save an FP64 nest (an exact nest raises the residual to the power d+1,
+//      Appendix 2; the rms, a mean dominated by the slowest modes, falls with
+//      a smaller effective order p, measured from the last two FP32 nests, and
+//      the FP64 nests needed from rms r are ceil(log_p(log tol / log r))), or
+//      until an FP32 nest no longer takes 5% off the rms or the rms stagnates
+//      in the asymptotic regime (sqrt(N) rms_{k-1} < 0.1 and rms_k >=
+//      rms_{k-1} / 2) — the FP32 rounding floor.  A loose tolerance (tol >= 1e-4, far above that floor:
 //      a preconditioner) is met by the FP32 iterate itself: the phase then
 //      runs until the FP32 rms is below tol, and phase D only confirms it.
 //   D  FP64 residual and FP64 refinement nests until rms < tol.
@@ -108,6 +111,13 @@ MixedWs carve(void* base, int64_t n, int depth) {
     hipError_t e_ = (expr);                   \
     if (e_ != hipSuccess) return NN_ERR_HIP; \
   } while (0)
+
+// FP64 nests predicted to take the rms r below tol at effective order p.
+int fp64_nests(double r, double p, double tol) {
+  if (!(r >= tol)) return 0;
+  if (r >= 1.0) return 1 << 20;
+  return (int)ceil(log(log(tol) / log(r)) / log(p));
+}
 
 struct Run {
   nn_ctx* ctx;
@@ -264,9 +274,21 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
     if (!isfinite(rms)) return finish(NN_ERR_NONFINITE, rms);
     if (rms >= 1.0 && rms > rms_prev) return finish(NN_ERR_DIVERGED, rms);
     if (iters >= max_iter) break;
-    if (prm->tol >= kLooseTol ? rms < prm->tol                              // FP32 meets it
-                              : pow(rms, (double)((r.d + 1) * (r.d + 1))) < prm->tol)  // two FP64 nests
-      break;
+    // no progress (rms at least 0.95 of the previous one): the FP32 floor,
+    // wherever it lies (the floor rule below needs sqrt(N) rms < 0.1)
+    if (isfinite(rms_prev) && rms >= 0.95 * rms_prev) break;
+    if (prm->tol >= kLooseTol) {
+      if (rms < prm->tol) break;  // the FP32 iterate meets a loose tolerance
+    } else {
+      // Another FP32 nest (half the cost of an FP64 one) is taken while it is
+      // predicted to save an FP64 nest.  The rms falls per nest with an
+      // effective order p below d + 1 (the slowest modes dominate the mean),
+      // measured on the previous FP32 nest.
+      double p = (double)(r.d + 1);
+      if (isfinite(rms_prev) && rms_prev < 1.0 && rms < rms_prev && rms > 0.0)
+        p = std::min(std::max(log(rms) / log(rms_prev), 1.5), (double)(r.d + 1));
+      if (fp64_nests(pow(rms, p), p, prm->tol) >= fp64_nests(rms, p, prm->tol)) break;
+    }
     if (sqrt((double)n) * rms_prev < 0.1 && rms >= 0.5 * rms_prev) break;  // FP32 floor
     rms_prev = rms;
     float* U[2] = {w.U32[0], w.U32[1]};
