@@ -361,22 +361,28 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
   }
 }
 
-// Split-K epilogue, one workgroup per output tile: C = alpha * sum_s W_s +
-// E + diag * I with the partials summed in split order, and the tile's sum
-// of squares in partials[tile] (the unsplit kernel's indexing).
+// Split-K epilogue, kSplitChunks workgroups per output tile (each a band of
+// the tile's rows): C = alpha * sum_s W_s + E + diag * I with the partials
+// summed in split order; each band's sum of squares goes to ssbuf and
+// splitk_tile_ss adds a tile's bands in order into partials[tile] (the
+// unsplit kernel's indexing).
+constexpr int kSplitChunks = 8;
+
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) splitk_epilogue(GemmArgs p, int split, int bm, int bn,
-                                                       int tiles_n) {
+                                                       int tiles_n, double* ssbuf) {
   __shared__ double red[256];
-  const int tile = blockIdx.x;
-  const int64_t m0 = (int64_t)(tile / tiles_n) * bm, n0 = (int64_t)(tile % tiles_n) * bn;
+  const int tile = blockIdx.x / kSplitChunks, band = blockIdx.x % kSplitChunks;
+  const int rows = bm / kSplitChunks;
+  const int64_t m0 = (int64_t)(tile / tiles_n) * bm + band * rows;
+  const int64_t n0 = (int64_t)(tile % tiles_n) * bn;
   const int64_t M = p.M, N = p.N;
   const T* __restrict__ Wp = static_cast<const T*>(p.work);
   T* __restrict__ C = static_cast<T*>(p.C);
   const T* __restrict__ E = static_cast<const T*>(p.E);
   const T alpha = (T)p.alpha, diag = (T)p.diag;
   double ss = 0.0;
-  for (int e = threadIdx.x; e < bm * bn; e += 256) {
+  for (int e = threadIdx.x; e < rows * bn; e += 256) {
     const int64_t r = m0 + e / bn, c = n0 + e % bn;
     if (r < M && c < N) {
       T v = T(0);
@@ -395,8 +401,17 @@ __global__ void __launch_bounds__(256) splitk_epilogue(GemmArgs p, int split, in
       if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) p.partials[tile] = red[0];
+    if (threadIdx.x == 0) ssbuf[blockIdx.x] = red[0];
   }
+}
+
+__global__ void __launch_bounds__(256) splitk_tile_ss(const double* ssbuf, int ntile,
+                                                      double* partials) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= ntile) return;
+  double v = 0.0;
+  for (int b = 0; b < kSplitChunks; ++b) v += ssbuf[t * kSplitChunks + b];
+  partials[t] = v;
 }
 
 struct TileShape {
@@ -441,9 +456,16 @@ hipError_t launch_one(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, OCC, VEC, CPLX, false>), dim3(grid),
                        dim3(WM * WN * 64), 0, s, b, plan.tiles_m, plan.tiles_n);
-  if (split > 1)
-    hipLaunchKernelGGL((splitk_epilogue<T, CPLX>), dim3(ntile), dim3(256), 0, s, a, split, BM, BN,
-                       plan.tiles_n);
+  if (split > 1) {
+    static_assert(BM % kSplitChunks == 0, "row bands of a tile");
+    double* ssbuf = reinterpret_cast<double*>(static_cast<char*>(a.work) +
+                                              (size_t)split * a.M * a.N * sizeof(T));
+    hipLaunchKernelGGL((splitk_epilogue<T, CPLX>), dim3(ntile * kSplitChunks), dim3(256), 0, s, a,
+                       split, BM, BN, plan.tiles_n, ssbuf);
+    if (a.partials)
+      hipLaunchKernelGGL(splitk_tile_ss, dim3((ntile + 255) / 256), dim3(256), 0, s, ssbuf, ntile,
+                         a.partials);
+  }
   return hipGetLastError();
 }
 
@@ -524,7 +546,9 @@ GemmPlan plan_gemm_k(Elem e, int64_t M, int64_t N, int64_t K) {
 
 size_t gemm_work_bytes(const GemmPlan& plan, Elem e, int64_t M, int64_t N) {
   if (plan.split <= 1) return 0;
-  return (size_t)plan.split * (size_t)M * (size_t)N * (e == Elem::F64 ? 8 : 4);
+  // split partial products, then one sum of squares per tile row band
+  return (size_t)plan.split * (size_t)M * (size_t)N * (e == Elem::F64 ? 8 : 4) +
+         sizeof(double) * (size_t)plan.num_tiles() * kSplitChunks;
 }
 
 hipError_t launch_gemm(Elem e, bool cplx, const GemmPlan& plan, const GemmArgs& a,

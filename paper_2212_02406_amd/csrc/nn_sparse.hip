@@ -90,12 +90,15 @@ __global__ void __launch_bounds__(256) csr_check_cols(const int32_t* ci, int64_t
   if (threadIdx.x == 0) part[blockIdx.x] = bad;
 }
 
-// out[0] = sum (op 0) or NaN-propagating min (op 1) of vals[0..count), fixed order.
+// out[b] = sum (op 0) or NaN-propagating min (op 1) of the values a block
+// strides over (block b of the grid, fixed order): the first level of a
+// reduction over long vectors, or the whole of it with one block.
 __global__ void __launch_bounds__(256) reduce_one(const double* vals, int64_t count, int op,
                                                   double* out) {
   __shared__ double red[256];
   double acc = op == 0 ? 0.0 : INFINITY;
-  for (int64_t i = threadIdx.x; i < count; i += 256) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
     const double v = vals[i];
     if (op == 0) acc += v;
     else acc = (isnan(acc) || isnan(v)) ? NAN : (v < acc ? v : acc);
@@ -109,7 +112,20 @@ __global__ void __launch_bounds__(256) reduce_one(const double* vals, int64_t co
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ void norm_finish(const double* sumsq, double mult, double* out) {
+  if (threadIdx.x == 0) out[0] = mult * sqrt(sumsq[0]);
+}
+
+// Two-level reduction of a long vector into out[0] (part: kSpBlocks scratch).
+hipError_t reduce_long(const double* vals, int64_t count, int op, double* part, double* out,
+                       hipStream_t s) {
+  const int nb = (int)std::min<int64_t>((count + 255) / 256, kSpBlocks);
+  hipLaunchKernelGGL(reduce_one, dim3(nb), dim3(256), 0, s, vals, count, op, part);
+  hipLaunchKernelGGL(reduce_one, dim3(1), dim3(256), 0, s, part, (int64_t)nb, op, out);
+  return hipGetLastError();
 }
 
 // Diagonal of W (duplicates summed): dre[r] = Re d_r, dab[r] = |d_r| (NaN if
@@ -483,13 +499,21 @@ struct Launch {
     double* xa = w.pa;
     double* xb = w.pb;
     double* nrm = w.scal + 8;
+    // ||.|| of an n-vector of squares: two-level sum, then the root
+    auto norm = [&](double* out) {
+      hipError_t e = reduce_long(w.dre, n, 0, w.part, w.scal + 2, s);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(norm_finish, dim3(1), dim3(64), 0, s, w.scal + 2, 1.0, out);
+        e = hipGetLastError();
+      }
+      return e;
+    };
     hipError_t e = launch_power_vector(CPLX, xa, w.dre, n, s);
-    if (e != hipSuccess) return e;
-    e = launch_norm_reduce(w.dre, n, 1.0, nrm, s);
+    if (e == hipSuccess) e = norm(nrm);
     for (int j = 0; j <= k && e == hipSuccess; ++j) {
       hipLaunchKernelGGL((csr_power_step<T, CPLX>), dim3((unsigned)((n + 255) / 256)), dim3(256),
                          0, s, rp, ci, static_cast<const T*>(v), n, xa, nrm + j, xb, w.dre);
-      e = launch_norm_reduce(w.dre, n, 1.0, j == k ? w.scal : nrm + j + 1, s);
+      e = norm(j == k ? w.scal : nrm + j + 1);
       std::swap(xa, xb);
     }
     return e;
@@ -685,8 +709,7 @@ nn_status nn_solve_sparse(nn_ctx* ctx, const int32_t* row_ptr, const int32_t* co
     hipLaunchKernelGGL(scal_ops, dim3(1), dim3(64), 0, s, w.scal, 1, (double)prm->power_k);
   } else {
     HIP_TRY(ops.diag(row_ptr, col_idx, values, n, w, jac, s));
-    hipLaunchKernelGGL(reduce_one, dim3(1), dim3(256), 0, s, jac ? w.dab : w.dre, n,
-                       jac ? 1 : 0, w.scal);
+    HIP_TRY(reduce_long(jac ? w.dab : w.dre, n, jac ? 1 : 0, w.part, w.scal, s));
     if (!jac) hipLaunchKernelGGL(scal_ops, dim3(1), dim3(64), 0, s, w.scal, 0, 0.0);
   }
   HIP_TRY(hipGetLastError());
