@@ -11,9 +11,14 @@
 //    (a whole 4-wave workgroup each) and "wave" matrices (K <= wave_max_k,
 //    one wave each, four per work item), and the reset of the work counter.
 //  * persistent kernel: each workgroup pops work items from the counter
-//    until the queue is empty (every wave reaches that exit).  A matrix lives
-//    entirely in LDS (buffers G, X, R, U) for all its nests; global memory is
-//    touched only to load G and store X and the per-matrix info.
+//    until the queue is empty (every wave reaches that exit).  A matrix's
+//    iterate and residual live in LDS for all its nests (buffers X and R, plus
+//    U for depth >= 3); G is staged from global memory (L2 after the first
+//    read) into R's buffer before each residual, which the product then
+//    overwrites, and U = R + R R overwrites R at depth 2.  Two buffers instead
+//    of four halve the LDS of a K = 64 complex matrix to 68 KB, and the
+//    register budget is held to 256 per lane, so two workgroups — two waves
+//    per SIMD — share a CU.
 //  * every product is an LDS-to-register GEMM on v_mfma_f32_16x16x4_f32; a
 //    complex product is the real product of the interleaved left factor with
 //    the real 2K x 2K form of the right factor, expanded on read (row 2k is
@@ -252,6 +257,10 @@ __device__ __forceinline__ bool shared_rows(int K, bool cplx, int NB) {
   return nbn % NB == 0;
 }
 
+// LDS buffers per matrix: X and R (R also holds the staged G and, at depth
+// <= 2, U), plus U for depth >= 3.
+__device__ __host__ __forceinline__ int lds_nbufs(int depth) { return depth >= 3 ? 3 : 2; }
+
 // The whole NN run for one matrix: load, start iterate, `iters` nests of
 // depth d, final residual, store.
 template <bool CPLX, int NB, bool SH>
@@ -260,20 +269,24 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
                            int buf, int bufstride, const Group& g, nn_info_dev* info) {
   const int cols = CPLX ? 2 * K : K;
   const int ld = lds_ld(K, CPLX);
-  const int Gs = buf, Xs = buf + bufstride, Rs = buf + 2 * bufstride, Us = buf + 3 * bufstride;
+  const int Xs = buf, Rs = buf + bufstride, Us = depth >= 3 ? buf + 2 * bufstride : Rs;
+  const int Gs = Rs;  // G is staged into R's buffer
   double* red = s_red[g.redrow];
   const int nthr = g.G * 64;
   if ((K & 15) || (cols & 15)) {  // ragged size: the padding must read as zero
     const int nb = lds_buf(K, CPLX);
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < lds_nbufs(depth); ++q)
       for (int e = g.gtid; e < nb; e += nthr) smem[buf + q * bufstride + e] = 0.f;
     g.sync();
   }
-  for (int e = g.gtid; e < K * cols; e += nthr) {
-    const int r = e / cols, c = e - r * cols;
-    smem[Gs + r * ld + c] = Ag[e];
-  }
-  g.sync();
+  // G (row-major, K x cols floats) into R's buffer: waves over rows, lanes
+  // over columns (coalesced, no index division)
+  auto stage_g = [&]() {
+    for (int r = g.gw; r < K; r += g.G)
+      for (int c = g.lane; c < cols; c += 64) smem[Gs + r * ld + c] = Ag[r * cols + c];
+    g.sync();
+  };
+  stage_g();
   // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G.
   double den;
   if (x0 == NN_X0_TRANSPOSE) {
@@ -327,6 +340,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   }
   g.sync();
   for (int it = 0; it < iters; ++it) {
+    if (it > 0) stage_g();  // the first nest finds G staged by the start
     lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, nullptr);  // R = I - G X
     int U = Rs;
     for (int m = 1; m < depth; ++m) {  // U_{m+1} = R + R U_m
@@ -336,12 +350,11 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     lds_gemm_nb<CPLX, NB, SH>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
   }
   double ss = 0.0;
+  if (iters > 0) stage_g();
   lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, &ss);
   const double rms = sqrt(ss / (double)K);
-  for (int e = g.gtid; e < K * cols; e += nthr) {
-    const int r = e / cols, c = e - r * cols;
-    Xg[e] = smem[Xs + r * ld + c];
-  }
+  for (int r = g.gw; r < K; r += g.G)
+    for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + c];
   if (info && g.gtid == 0) {
     nn_info_dev d;
     d.iters = iters;
@@ -405,8 +418,12 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
   }
 }
 
+// waves_per_eu(2): at most 256 registers per lane (VGPRs and AGPRs), so two
+// waves share a SIMD; the fully inlined size-class paths otherwise take
+// about 400 and hold the SIMD to one wave (measured: 2.53 -> 1.86 ms for
+// 4096 K = 64 complex matrices, a few hundred bytes of scratch spills).
 template <bool CPLX>
-__global__ void __launch_bounds__(kThreads) batched_nn(const float* A, float* X,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) batched_nn(const float* A, float* X,
                                                        const int64_t* offsets,
                                                        const int32_t* sizes, const int32_t* perm,
                                                        BatchHdr* hdr, int max_n, int wave_max_k,
@@ -452,7 +469,7 @@ __global__ void __launch_bounds__(kThreads) batched_nn(const float* A, float* X,
         const Group g{0, 1, lane, lane, wave, false};
         const int64_t off = offsets[b] * cm;
         const int K = sizes[b];
-        const int base = wave * 4 * wave_stride;
+        const int base = wave * lds_nbufs(depth) * wave_stride;
         nn_info_dev* inf = info ? info + b : nullptr;
         const int nbw = blocks_per_wave(K, CPLX, 1);
         const bool sh = shared_rows(K, CPLX, nbw);
@@ -474,10 +491,11 @@ __global__ void __launch_bounds__(kThreads) batched_nn(const float* A, float* X,
   }
 }
 
-size_t lds_bytes(bool cplx, int max_n, int wave_max_k) {
-  const size_t big = 4 * (size_t)lds_buf(max_n, cplx);
+size_t lds_bytes(bool cplx, int max_n, int wave_max_k, int depth) {
+  const size_t nb = (size_t)lds_nbufs(depth);
+  const size_t big = nb * (size_t)lds_buf(max_n, cplx);
   const int wk = wave_max_k > 0 ? wave_max_k : 1;
-  const size_t small = 16 * (size_t)lds_buf(wk, cplx);
+  const size_t small = 4 * nb * (size_t)lds_buf(wk, cplx);  // four wave matrices
   return sizeof(float) * (big > small ? big : small);
 }
 
@@ -497,7 +515,7 @@ hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* of
                      hdr, perm, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = lds_bytes(cplx, max_n, wave_max_k);
+  const size_t lds = lds_bytes(cplx, max_n, wave_max_k, depth);
   if (cplx) {
     hipLaunchKernelGGL(batched_nn<true>, dim3(grid), dim3(kThreads), lds, s,
                        static_cast<const float*>(A), static_cast<float*>(X), offsets, sizes, perm,
@@ -519,9 +537,9 @@ hipError_t batched_allow_lds() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
-size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k) {
+size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k, int depth) {
   if (wave_max_k > max_n) wave_max_k = max_n;
-  return lds_bytes(dt == NN_C64, max_n, wave_max_k);
+  return lds_bytes(dt == NN_C64, max_n, wave_max_k, depth);
 }
 
 }  // namespace nn

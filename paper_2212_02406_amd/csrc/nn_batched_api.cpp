@@ -59,8 +59,8 @@ void store(nn_ctx* ctx, const BatchedTune& t) {
   ctx->tune[0] = t;
 }
 
-int max_wg_per_cu(nn_dtype dt, int max_n, int wave_max_k) {
-  const size_t lds = batched_lds_bytes(dt, max_n, wave_max_k) + 4 * 1024;  // + static LDS
+int max_wg_per_cu(nn_dtype dt, int max_n, int wave_max_k, int depth) {
+  const size_t lds = batched_lds_bytes(dt, max_n, wave_max_k, depth) + 4 * 1024;  // + static LDS
   return std::max(1, (int)std::min<size_t>(8, kLdsPerCu / lds));
 }
 
@@ -136,7 +136,7 @@ BatchedGraph make_key(nn_ctx* ctx, const void* A, void* X, const int64_t* offset
   k.x0 = p->x0;
   k.iters = p->fixed_iter;
   k.wave_max_k = std::min({t.wave_max_k, max_n, 32});
-  const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(dt, max_n, k.wave_max_k));
+  const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(dt, max_n, k.wave_max_k, p->depth));
   k.grid = std::max(1, std::min(batch, ctx->num_cus * per_cu));
 #ifdef NN_DIAG_GRID
   k.grid = NN_DIAG_GRID;
@@ -182,7 +182,7 @@ nn_status nn_batched_autotune(nn_ctx* ctx, const void* A_packed, void* X_packed,
   float best_t = INFINITY;
   for (int wk : waves) {
     if (wk > max_n) continue;
-    const int cap = max_wg_per_cu(dtype, max_n, wk);
+    const int cap = max_wg_per_cu(dtype, max_n, wk, params->depth);
     for (int per_cu = 1; per_cu <= cap; per_cu *= 2) {
       BatchedTune t;
       t.dtype = dtype;

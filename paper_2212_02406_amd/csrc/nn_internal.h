@@ -148,7 +148,7 @@ hipError_t launch_sumsq(const void* src, bool f64, int64_t ld, int64_t rows, int
 // Batched persistent path: plan kernel + persistent kernel on stream s.
 // Matrices of size <= wave_max_k (<= 32) get one wave each; grid workgroups.
 size_t batched_ws_bytes(int32_t batch);
-size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k);
+size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k, int depth);
 hipError_t batched_allow_lds();  // raise the dynamic LDS limit (call outside capture)
 hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* offsets,
                           const int32_t* sizes, int32_t batch, int32_t max_n, int depth, int x0,
