@@ -8,8 +8,8 @@
 // Structure:
 //  * plan kernel (one block): counting sort of the matrices by size, largest
 //    first (longest-processing-time order), the split into "group" matrices
-//    (a whole 4-wave workgroup each) and "wave" matrices (K <= wave_max_k,
-//    one wave each, four per work item), and the reset of the work counter.
+//    (a whole 8-wave workgroup each) and "wave" matrices (K <= wave_max_k,
+//    one wave each, eight per work item), and the reset of the work counter.
 //  * persistent kernel: each workgroup pops work items from the counter
 //    until the queue is empty (every wave reaches that exit).  A matrix's
 //    iterate and residual live in LDS for all its nests (buffers X and R, plus
@@ -38,8 +38,12 @@ namespace {
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxN = 64;
-constexpr int kThreads = 256;
-constexpr int kMaxBlocks = 8;  // 16x16 output blocks per wave (K = 64 complex over 4 waves)
+// Eight waves per workgroup: a "group" matrix is shared by all eight (a K = 64
+// complex product is 32 output blocks, 4 per wave), a "wave" item holds
+// eight matrices of one wave each.
+constexpr int kThreads = 512;
+constexpr int kWaves = 8;
+constexpr int kMaxBlocks = 8;  // 16x16 output blocks per wave
 
 struct BatchHdr {
   int32_t counter;
@@ -67,7 +71,7 @@ __device__ __host__ __forceinline__ int lds_buf(int K, bool cplx) {
 // reduction scratch.  Everything below addresses LDS through these arrays and
 // integer offsets, so the accesses compile to ds_read/ds_write.
 extern __shared__ __attribute__((aligned(16))) float smem[];
-__shared__ double s_red[4][8 + 2 * kMaxN];
+__shared__ double s_red[kWaves][8 + 2 * kMaxN];
 
 struct Group {
   int gw;      // wave index inside the group
@@ -407,7 +411,7 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
     hdr->counter = 0;
     hdr->n_large = large;
     hdr->n_small = small;
-    hdr->n_items = large + (small + 3) / 4;
+    hdr->n_items = large + (small + kWaves - 1) / kWaves;
     hdr->bad = bad;
   }
   __syncthreads();
@@ -418,12 +422,15 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
   }
 }
 
-// waves_per_eu(2): at most 256 registers per lane (VGPRs and AGPRs), so two
-// waves share a SIMD; the fully inlined size-class paths otherwise take
-// about 400 and hold the SIMD to one wave (measured: 2.53 -> 1.86 ms for
-// 4096 K = 64 complex matrices, a few hundred bytes of scratch spills).
+// waves_per_eu(4): at most 128 registers per lane (VGPRs and AGPRs), so two
+// eight-wave workgroups (four waves per SIMD) share a CU; the fully inlined
+// size-class paths otherwise take about 400 and hold a SIMD to one wave.
+// Measured on 4096 K = 64 complex matrices: 2.53 ms (four waves per
+// workgroup, ~400 registers), 1.84 ms (four waves, 256 registers, two
+// workgroups per CU), 1.58 ms (eight waves, 128 registers, two per CU; about
+// 1 KB of scratch spills per lane).
 template <bool CPLX>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) batched_nn(const float* A, float* X,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) batched_nn(const float* A, float* X,
                                                        const int64_t* offsets,
                                                        const int32_t* sizes, const int32_t* perm,
                                                        BatchHdr* hdr, int max_n, int wave_max_k,
@@ -444,11 +451,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     if (item >= n_items) break;
     if (item < n_large) {
       const int b = perm[item];
-      const Group g{wave, 4, lane, tid, 0, true};
+      const Group g{wave, kWaves, lane, tid, 0, true};
       const int64_t off = offsets[b] * cm;
       const int K = sizes[b];
       nn_info_dev* inf = info ? info + b : nullptr;
-      const int nbw = blocks_per_wave(K, CPLX, 4);
+      const int nbw = blocks_per_wave(K, CPLX, kWaves);
       const bool sh = shared_rows(K, CPLX, nbw);
 #define NN_ONE(NB, SH) invert_one<CPLX, NB, SH>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf)
       switch (nbw * 2 + (sh ? 1 : 0)) {
@@ -463,7 +470,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
       }
 #undef NN_ONE
     } else {
-      const int idx = n_large + 4 * (item - n_large) + wave;
+      const int idx = n_large + kWaves * (item - n_large) + wave;
       if (idx < n_large + n_small) {
         const int b = perm[idx];
         const Group g{0, 1, lane, lane, wave, false};
@@ -495,7 +502,7 @@ size_t lds_bytes(bool cplx, int max_n, int wave_max_k, int depth) {
   const size_t nb = (size_t)lds_nbufs(depth);
   const size_t big = nb * (size_t)lds_buf(max_n, cplx);
   const int wk = wave_max_k > 0 ? wave_max_k : 1;
-  const size_t small = 4 * nb * (size_t)lds_buf(wk, cplx);  // four wave matrices
+  const size_t small = kWaves * nb * (size_t)lds_buf(wk, cplx);  // one wave matrix per wave
   return sizeof(float) * (big > small ? big : small);
 }
 
