@@ -338,10 +338,19 @@ size_t nn_batched_workspace_size(int32_t batch, nn_dtype dtype);
  *   offsets (int64), sizes (int32): device arrays of length `batch`;
  *                        1 <= sizes[b] <= max_n.
  *   max_n                upper bound of sizes (<= 64).
- *   params               fixed_iter > 0 required (tolerance mode is not
- *                        offered for batches); x0 TRANSPOSE or
- *                        SCALED_IDENTITY.
- *   per_matrix           device array of `batch` nn_info_dev, or NULL.
+ *   params               fixed_iter > 0: exactly that many nests per matrix;
+ *                        fixed_iter == 0: tolerance mode, each matrix on its
+ *                        own: nn_invert's stopping rules (the rms tests of
+ *                        its tolerance mode, with sqrt(size) for sqrt(n))
+ *                        run on the device after every residual, with
+ *                        params.tol and 1 <= params.max_iter <= 4096;
+ *                        x0 TRANSPOSE, SCALED_IDENTITY or GIVEN (X_packed
+ *                        holds each matrix's start on entry).  prec PLAIN,
+ *                        flags 0.
+ *   per_matrix           device array of `batch` nn_info_dev, or NULL:
+ *                        nests applied, status (nn_invert's codes; STAGNATED
+ *                        returns the iterate before the last nest) and rms
+ *                        of the returned iterate.
  * Asynchronous on the context stream; nothing is read back.  Each matrix's
  * result depends only on that matrix (never on the rest of the batch).
  * Supported dtypes: C64, F32. */

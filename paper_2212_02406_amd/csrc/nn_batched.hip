@@ -28,6 +28,10 @@
 //  * results depend only on the matrix and its size class: block-to-wave
 //    assignment and summation orders are fixed, so a matrix gives the same
 //    bits alone or in any batch.
+//  * two control modes: a fixed number of nests, or a tolerance mode in which
+//    each matrix applies the stopping rules of the single-matrix path on the
+//    device after every residual (its own tolerance and nest limit), so the
+//    matrices of one launch stop independently.
 #include <math.h>
 
 #include "nn_internal.h"
@@ -265,12 +269,20 @@ __device__ __forceinline__ bool shared_rows(int K, bool cplx, int NB) {
 // <= 2, U), plus U for depth >= 3.
 __device__ __host__ __forceinline__ int lds_nbufs(int depth) { return depth >= 3 ? 3 : 2; }
 
-// The whole NN run for one matrix: load, start iterate, `iters` nests of
-// depth d, final residual, store.
+// The whole NN run for one matrix: load, start iterate, then either `iters`
+// nests and a final residual (iters > 0) or the tolerance-mode loop (iters ==
+// 0): after each residual R_k = I - G X_k, in this order, rms_k not finite ->
+// NONFINITE; rms_k < tol -> OK with X_k; k > 0, rms_k >= 1 and rising ->
+// DIVERGED; k > 0, sqrt(K) rms_{k-1} < 0.1 and rms_k >= rms_{k-1} -> STAGNATED
+// with X_{k-1}; k == max_iter -> NOT_CONVERGED; else one nest.  X_{k-1} is
+// kept in global memory: X_k is written out before its nest whenever
+// sqrt(K) rms_k < 0.1, the only case in which the next test can fire.  Every
+// decision uses the group-reduced sum, identical in all lanes, so the group's
+// control flow stays uniform.
 template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, int depth, int x0,
-                                           int iters,
-                           int buf, int bufstride, const Group& g, nn_info_dev* info) {
+                                           int iters, double tol, int max_iter, int buf,
+                                           int bufstride, const Group& g, nn_info_dev* info) {
   const int cols = CPLX ? 2 * K : K;
   const int ld = lds_ld(K, CPLX);
   const int Xs = buf, Rs = buf + bufstride, Us = depth >= 3 ? buf + 2 * bufstride : Rs;
@@ -290,9 +302,14 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       for (int c = g.lane; c < cols; c += 64) smem[Gs + r * ld + c] = Ag[r * cols + c];
     g.sync();
   };
+  auto store_x = [&]() {
+    for (int r = g.gw; r < K; r += g.G)
+      for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + c];
+  };
   stage_g();
-  // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G.
-  double den;
+  // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G;
+  // NN_X0_GIVEN reads X_0 from Xg.
+  double den = 1.0;
   if (x0 == NN_X0_TRANSPOSE) {
     if (g.gtid < 2 * K) {
       const bool row = g.gtid < K;
@@ -319,7 +336,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       n1 = c > n1 ? c : n1;
     }
     den = bad ? NAN : n1 * ninf;
-  } else {
+  } else if (x0 == NN_X0_SCALED_IDENTITY) {
     double t = 0.0;
     for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + (CPLX ? 2 * i : i)];
     den = t;
@@ -327,44 +344,85 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   const bool den_ok = isfinite(den) && den > 0.0;
   const float s = (float)(1.0 / den);
   g.sync();
-  for (int e = g.gtid; e < K * cols; e += nthr) {
-    const int r = e / cols, c = e - r * cols;
-    float v;
-    if (x0 == NN_X0_TRANSPOSE) {
-      if constexpr (CPLX) {
-        const int j = c >> 1;  // X[r][j] = conj(G[j][r]) * s
-        v = (c & 1) ? -smem[Gs + j * ld + 2 * r + 1] * s : smem[Gs + j * ld + 2 * r] * s;
+  if (x0 == NN_X0_GIVEN) {
+    for (int r = g.gw; r < K; r += g.G)
+      for (int c = g.lane; c < cols; c += 64) smem[Xs + r * ld + c] = Xg[r * cols + c];
+  } else {
+    for (int e = g.gtid; e < K * cols; e += nthr) {
+      const int r = e / cols, c = e - r * cols;
+      float v;
+      if (x0 == NN_X0_TRANSPOSE) {
+        if constexpr (CPLX) {
+          const int j = c >> 1;  // X[r][j] = conj(G[j][r]) * s
+          v = (c & 1) ? -smem[Gs + j * ld + 2 * r + 1] * s : smem[Gs + j * ld + 2 * r] * s;
+        } else {
+          v = smem[Gs + c * ld + r] * s;
+        }
       } else {
-        v = smem[Gs + c * ld + r] * s;
+        v = (CPLX ? (c == 2 * r) : (c == r)) ? s : 0.f;
       }
-    } else {
-      v = (CPLX ? (c == 2 * r) : (c == r)) ? s : 0.f;
+      smem[Xs + r * ld + c] = v;
     }
-    smem[Xs + r * ld + c] = v;
   }
   g.sync();
-  for (int it = 0; it < iters; ++it) {
-    if (it > 0) stage_g();  // the first nest finds G staged by the start
-    lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, nullptr);  // R = I - G X
-    int U = Rs;
-    for (int m = 1; m < depth; ++m) {  // U_{m+1} = R + R U_m
-      lds_gemm_nb<CPLX, NB, SH>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr);
-      U = Us;
+  const bool fixed = iters > 0;
+  const double sqk = sqrt((double)K);
+  int k = 0, status = NN_OK;
+  double rms = NAN, rms_prev = NAN;
+  bool use_prev = false;
+  if (!fixed && !den_ok) {
+    status = isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE;
+  } else {
+    for (;;) {
+      if (k > 0) stage_g();  // the first residual finds G staged by the start
+      double ss = 0.0;
+      const bool want = !fixed || k == iters;
+      lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, want ? &ss : nullptr);  // R = I - G X
+      if (fixed) {
+        if (k == iters) {
+          rms = sqrt(ss / (double)K);
+          status = !den_ok ? (isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE)
+                           : (isfinite(rms) ? NN_OK : NN_ERR_NONFINITE);
+          break;
+        }
+      } else {
+        rms = sqrt(ss / (double)K);
+        if (!isfinite(rms)) {
+          status = NN_ERR_NONFINITE;
+          break;
+        }
+        if (rms < tol) break;
+        if (k > 0 && rms >= 1.0 && rms > rms_prev) {
+          status = NN_ERR_DIVERGED;
+          break;
+        }
+        if (k > 0 && sqk * rms_prev < 0.1 && rms >= rms_prev) {
+          status = NN_STAGNATED;
+          use_prev = true;
+          break;
+        }
+        if (k >= max_iter) {
+          status = NN_NOT_CONVERGED;
+          break;
+        }
+        if (sqk * rms < 0.1) store_x();  // X_k, in case the next nest stagnates
+      }
+      int U = Rs;
+      for (int m = 1; m < depth; ++m) {  // U_{m+1} = R + R U_m
+        lds_gemm_nb<CPLX, NB, SH>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr);
+        U = Us;
+      }
+      lds_gemm_nb<CPLX, NB, SH>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
+      rms_prev = rms;
+      ++k;
     }
-    lds_gemm_nb<CPLX, NB, SH>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
   }
-  double ss = 0.0;
-  if (iters > 0) stage_g();
-  lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, &ss);
-  const double rms = sqrt(ss / (double)K);
-  for (int r = g.gw; r < K; r += g.G)
-    for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + c];
+  if (!use_prev) store_x();
   if (info && g.gtid == 0) {
     nn_info_dev d;
-    d.iters = iters;
-    d.rms = rms;
-    d.status = !den_ok ? (isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE)
-                       : (isfinite(rms) ? NN_OK : NN_ERR_NONFINITE);
+    d.iters = use_prev ? k - 1 : k;
+    d.rms = use_prev ? rms_prev : rms;
+    d.status = status;
     *info = d;
   }
   g.sync();
@@ -430,17 +488,16 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
 // workgroups per CU), 1.58 ms (eight waves, 128 registers, two per CU; about
 // 1 KB of scratch spills per lane).
 template <bool CPLX>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) batched_nn(const float* A, float* X,
-                                                       const int64_t* offsets,
-                                                       const int32_t* sizes, const int32_t* perm,
-                                                       BatchHdr* hdr, int max_n, int wave_max_k,
-                                                       int depth, int x0, int iters,
-                                                       nn_info_dev* info) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
   __shared__ int item_s;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int cm = CPLX ? 2 : 1;
-  const int big_stride = lds_buf(max_n, CPLX);
-  const int wk = wave_max_k > 0 ? wave_max_k : 1;
+  const float* A = static_cast<const float*>(a.A);
+  float* X = static_cast<float*>(a.X);
+  const int64_t* xoffsets = a.xoffsets ? a.xoffsets : a.offsets;
+  const int big_stride = lds_buf(a.max_n, CPLX);
+  const int wk = a.wave_max_k > 0 ? a.wave_max_k : 1;
   const int wave_stride = lds_buf(wk, CPLX);
   const int n_items = hdr->n_items, n_large = hdr->n_large, n_small = hdr->n_small;
   for (;;) {
@@ -452,12 +509,16 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     if (item < n_large) {
       const int b = perm[item];
       const Group g{wave, kWaves, lane, tid, 0, true};
-      const int64_t off = offsets[b] * cm;
-      const int K = sizes[b];
-      nn_info_dev* inf = info ? info + b : nullptr;
+      const int64_t off = a.offsets[b] * cm, xoff = xoffsets[b] * cm;
+      const int K = a.sizes[b];
+      const double tol = a.tols ? a.tols[b] : a.tol;
+      const int mit = a.maxits ? a.maxits[b] : a.max_iter;
+      nn_info_dev* inf = a.info ? a.info + b : nullptr;
       const int nbw = blocks_per_wave(K, CPLX, kWaves);
       const bool sh = shared_rows(K, CPLX, nbw);
-#define NN_ONE(NB, SH) invert_one<CPLX, NB, SH>(A + off, X + off, K, depth, x0, iters, 0, big_stride, g, inf)
+#define NN_ONE(NB, SH)                                                                        \
+  invert_one<CPLX, NB, SH>(A + off, X + xoff, K, a.depth, a.x0, a.iters, tol, mit, 0, big_stride, \
+                           g, inf)
       switch (nbw * 2 + (sh ? 1 : 0)) {
         case 2:
         case 3: NN_ONE(1, true); break;  // one block per wave always shares its row
@@ -474,13 +535,17 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
       if (idx < n_large + n_small) {
         const int b = perm[idx];
         const Group g{0, 1, lane, lane, wave, false};
-        const int64_t off = offsets[b] * cm;
-        const int K = sizes[b];
-        const int base = wave * lds_nbufs(depth) * wave_stride;
-        nn_info_dev* inf = info ? info + b : nullptr;
+        const int64_t off = a.offsets[b] * cm, xoff = xoffsets[b] * cm;
+        const int K = a.sizes[b];
+        const double tol = a.tols ? a.tols[b] : a.tol;
+        const int mit = a.maxits ? a.maxits[b] : a.max_iter;
+        const int base = wave * lds_nbufs(a.depth) * wave_stride;
+        nn_info_dev* inf = a.info ? a.info + b : nullptr;
         const int nbw = blocks_per_wave(K, CPLX, 1);
         const bool sh = shared_rows(K, CPLX, nbw);
-#define NN_ONE(NB, SH) invert_one<CPLX, NB, SH>(A + off, X + off, K, depth, x0, iters, base, wave_stride, g, inf)
+#define NN_ONE(NB, SH)                                                                     \
+  invert_one<CPLX, NB, SH>(A + off, X + xoff, K, a.depth, a.x0, a.iters, tol, mit, base,   \
+                           wave_stride, g, inf)
         switch (nbw * 2 + (sh ? 1 : 0)) {
           case 2:
           case 3: NN_ONE(1, true); break;  // one block per wave always shares its row
@@ -510,27 +575,21 @@ size_t lds_bytes(bool cplx, int max_n, int wave_max_k, int depth) {
 
 size_t batched_ws_bytes(int32_t batch) { return 256 + ((size_t)batch * 4 + 255) / 256 * 256; }
 
-hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* offsets,
-                          const int32_t* sizes, int32_t batch, int32_t max_n, int depth, int x0,
-                          int iters, int wave_max_k, void* ws, nn_info_dev* info, int grid,
-                          hipStream_t s) {
-  BatchHdr* hdr = static_cast<BatchHdr*>(ws);
-  int32_t* perm = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
-  const bool cplx = dt == NN_C64;
-  if (wave_max_k > max_n) wave_max_k = max_n;
-  hipLaunchKernelGGL(batched_plan, dim3(1), dim3(1024), 0, s, sizes, batch, max_n, wave_max_k,
-                     hdr, perm, info);
+hipError_t launch_batched(const BatchedArgs& args, hipStream_t s) {
+  BatchedArgs a = args;
+  BatchHdr* hdr = static_cast<BatchHdr*>(a.ws);
+  int32_t* perm = reinterpret_cast<int32_t*>(static_cast<char*>(a.ws) + 256);
+  const bool cplx = a.dt == NN_C64;
+  if (a.wave_max_k > a.max_n) a.wave_max_k = a.max_n;
+  hipLaunchKernelGGL(batched_plan, dim3(1), dim3(1024), 0, s, a.sizes, a.batch, a.max_n,
+                     a.wave_max_k, hdr, perm, a.info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = lds_bytes(cplx, max_n, wave_max_k, depth);
+  const size_t lds = lds_bytes(cplx, a.max_n, a.wave_max_k, a.depth);
   if (cplx) {
-    hipLaunchKernelGGL(batched_nn<true>, dim3(grid), dim3(kThreads), lds, s,
-                       static_cast<const float*>(A), static_cast<float*>(X), offsets, sizes, perm,
-                       hdr, max_n, wave_max_k, depth, x0, iters, info);
+    hipLaunchKernelGGL(batched_nn<true>, dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
   } else {
-    hipLaunchKernelGGL(batched_nn<false>, dim3(grid), dim3(kThreads), lds, s,
-                       static_cast<const float*>(A), static_cast<float*>(X), offsets, sizes, perm,
-                       hdr, max_n, wave_max_k, depth, x0, iters, info);
+    hipLaunchKernelGGL(batched_nn<false>, dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
   }
   return hipGetLastError();
 }

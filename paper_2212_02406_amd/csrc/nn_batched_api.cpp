@@ -26,8 +26,12 @@ nn_status check_batched(nn_ctx* ctx, const void* A, const void* X, const int64_t
   if (A == X) return NN_ERR_ARG;
   if (dt != NN_C64 && dt != NN_F32) return NN_ERR_UNSUPPORTED;
   if (p->depth < 1 || p->depth > NN_MAX_DEPTH || p->flags != 0) return NN_ERR_ARG;
-  if (p->x0 != NN_X0_TRANSPOSE && p->x0 != NN_X0_SCALED_IDENTITY) return NN_ERR_UNSUPPORTED;
-  if (p->fixed_iter < 1) return NN_ERR_UNSUPPORTED;
+  if (p->x0 != NN_X0_TRANSPOSE && p->x0 != NN_X0_SCALED_IDENTITY && p->x0 != NN_X0_GIVEN)
+    return NN_ERR_UNSUPPORTED;
+  if (p->fixed_iter < 0) return NN_ERR_ARG;
+  if (p->fixed_iter == 0 &&
+      (!(p->tol >= 0.0) || p->max_iter < 1 || p->max_iter > kBatchedMaxIter))
+    return NN_ERR_ARG;
   if (p->prec != NN_PREC_PLAIN) return NN_ERR_UNSUPPORTED;
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || ws_bytes < batched_ws_bytes(batch))
     return NN_ERR_WORKSPACE;
@@ -74,7 +78,29 @@ bool same(const BatchedGraph& g, const BatchedGraph& k) {
   return g.exec && g.A == k.A && g.X == k.X && g.offsets == k.offsets && g.sizes == k.sizes &&
          g.ws == k.ws && g.info == k.info && g.batch == k.batch && g.max_n == k.max_n &&
          g.dtype == k.dtype && g.depth == k.depth && g.x0 == k.x0 && g.iters == k.iters &&
-         g.wave_max_k == k.wave_max_k && g.grid == k.grid;
+         g.wave_max_k == k.wave_max_k && g.grid == k.grid && g.tol == k.tol &&
+         g.max_iter == k.max_iter;
+}
+
+BatchedArgs args_of(const BatchedGraph& k) {
+  BatchedArgs a;
+  a.dt = (nn_dtype)k.dtype;
+  a.A = k.A;
+  a.X = k.X;
+  a.offsets = k.offsets;
+  a.sizes = k.sizes;
+  a.batch = k.batch;
+  a.max_n = k.max_n;
+  a.depth = k.depth;
+  a.x0 = k.x0;
+  a.iters = k.iters;
+  a.tol = k.tol;
+  a.max_iter = k.max_iter;
+  a.wave_max_k = k.wave_max_k;
+  a.ws = k.ws;
+  a.info = k.info;
+  a.grid = k.grid;
+  return a;
 }
 
 // Launch through the cached graph (capturing it first if the key changed).
@@ -84,9 +110,7 @@ nn_status run_graph(nn_ctx* ctx, const BatchedGraph& key) {
     if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) return NN_ERR_HIP;
     if (batched_allow_lds() != hipSuccess) return NN_ERR_HIP;
   }
-  return launch_batched((nn_dtype)key.dtype, key.A, key.X, key.offsets, key.sizes, key.batch,
-                        key.max_n, key.depth, key.x0, key.iters, key.wave_max_k, key.ws, key.info,
-                        key.grid, ctx->stream) == hipSuccess ? NN_OK : NN_ERR_HIP;
+  return launch_batched(args_of(key), ctx->stream) == hipSuccess ? NN_OK : NN_ERR_HIP;
 #endif
   if (!same(ctx->bgraph, key)) {
     drop_graph(ctx);
@@ -98,9 +122,7 @@ nn_status run_graph(nn_ctx* ctx, const BatchedGraph& key) {
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return NN_ERR_HIP;
-    hipError_t le = launch_batched((nn_dtype)key.dtype, key.A, key.X, key.offsets, key.sizes,
-                                   key.batch, key.max_n, key.depth, key.x0, key.iters,
-                                   key.wave_max_k, key.ws, key.info, key.grid, ctx->cap_stream);
+    hipError_t le = launch_batched(args_of(key), ctx->cap_stream);
     hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
     if (le != hipSuccess || ce != hipSuccess || !graph) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -135,6 +157,8 @@ BatchedGraph make_key(nn_ctx* ctx, const void* A, void* X, const int64_t* offset
   k.depth = p->depth;
   k.x0 = p->x0;
   k.iters = p->fixed_iter;
+  k.tol = p->fixed_iter > 0 ? 0.0 : p->tol;
+  k.max_iter = p->fixed_iter > 0 ? 0 : p->max_iter;
   k.wave_max_k = std::min({t.wave_max_k, max_n, 32});
   const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(dt, max_n, k.wave_max_k, p->depth));
   k.grid = std::max(1, std::min(batch, ctx->num_cus * per_cu));

@@ -150,10 +150,34 @@ hipError_t launch_sumsq(const void* src, bool f64, int64_t ld, int64_t rows, int
 size_t batched_ws_bytes(int32_t batch);
 size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k, int depth);
 hipError_t batched_allow_lds();  // raise the dynamic LDS limit (call outside capture)
-hipError_t launch_batched(nn_dtype dt, const void* A, void* X, const int64_t* offsets,
-                          const int32_t* sizes, int32_t batch, int32_t max_n, int depth, int x0,
-                          int iters, int wave_max_k, void* ws, nn_info_dev* info, int grid,
-                          hipStream_t s);
+// Arguments of one batched launch.  Matrix b: A at element offset offsets[b],
+// X at xoffsets[b] (offsets if null), size sizes[b].  iters > 0: exactly that
+// many nests; iters == 0: tolerance mode with tols[b] (tol if null) and
+// maxits[b] (max_iter if null).  x0: TRANSPOSE, SCALED_IDENTITY or GIVEN (X
+// holds X_0 on entry).
+struct BatchedArgs {
+  nn_dtype dt = NN_C64;
+  const void* A = nullptr;
+  void* X = nullptr;
+  const int64_t* offsets = nullptr;
+  const int64_t* xoffsets = nullptr;
+  const int32_t* sizes = nullptr;
+  const double* tols = nullptr;
+  const int32_t* maxits = nullptr;
+  int32_t batch = 0, max_n = 0;
+  int depth = 2, x0 = 0, iters = 0;
+  double tol = 0.0;
+  int max_iter = 0;
+  int wave_max_k = 16;
+  void* ws = nullptr;
+  nn_info_dev* info = nullptr;
+  int grid = 1;
+};
+hipError_t launch_batched(const BatchedArgs& a, hipStream_t s);
+
+// Upper bound of max_iter for the batched tolerance mode (bounds the
+// persistent kernel's run time).
+constexpr int kBatchedMaxIter = 4096;
 
 inline size_t elem_size(nn_dtype d) {
   switch (d) {
@@ -186,6 +210,8 @@ struct BatchedGraph {
   nn_info_dev* info = nullptr;
   int32_t batch = 0, max_n = 0;
   int dtype = -1, depth = 0, x0 = 0, iters = 0, wave_max_k = 0, grid = 0;
+  double tol = 0.0;
+  int max_iter = 0;
 };
 
 }  // namespace nn

@@ -474,18 +474,23 @@ def solve_sparse(indptr, indices, values, B, x0="identity", power_k=8, tol=1e-10
 
 
 def invert_batched(packed, offsets, sizes, max_n, depth=2, x0="transpose", fixed_iter=4,
-                   X=None, info=None, ctx: Context | None = None, ws=None, check=True):
+                   X=None, info=None, ctx: Context | None = None, ws=None, check=True,
+                   tol=0.0, max_iter=1):
     """nn_invert_batched on packed device buffers.  Returns (X_packed, info tensor).
 
     packed: 1-D complex64/float32 CUDA tensor; offsets int64 and sizes int32
     CUDA tensors.  info: (batch, 2) int32 + rms as a (batch,) float64 view of
     an nn_info_dev array (returned as a raw uint8 tensor of batch*16 bytes).
+    fixed_iter=0 selects the tolerance mode (tol, max_iter per matrix); with
+    x0="given", X (required) holds the start iterates on entry.
     """
     torch = _torch()
     batch = int(sizes.numel())
     dt = dtype_code(packed)
-    prm = make_params(depth, x0, 0.0, 1, fixed_iter)
+    prm = make_params(depth, x0, float(tol), int(max_iter), fixed_iter)
     if X is None:
+        if prm.x0 == NN_X0_GIVEN:
+            raise ValueError("x0='given' needs X holding the start iterates")
         X = torch.empty_like(packed)
     if info is None:
         info = torch.empty(batch * ctypes.sizeof(nn_info_dev), dtype=torch.uint8, device=packed.device)

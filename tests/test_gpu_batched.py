@@ -181,6 +181,140 @@ def test_argument_errors():
     with pytest.raises(nn.NNError):
         nn.invert_batched(P, O, S, 65, fixed_iter=4)
     with pytest.raises(nn.NNError):
-        nn.invert_batched(P, O, S, 64, fixed_iter=0)
+        nn.invert_batched(P, O, S, 64, fixed_iter=-1)
+    with pytest.raises(nn.NNError):  # tolerance mode needs 1 <= max_iter <= 4096, tol >= 0
+        nn.invert_batched(P, O, S, 64, fixed_iter=0, tol=1e-4, max_iter=0)
+    with pytest.raises(nn.NNError):
+        nn.invert_batched(P, O, S, 64, fixed_iter=0, tol=1e-4, max_iter=4097)
+    with pytest.raises(nn.NNError):
+        nn.invert_batched(P, O, S, 64, fixed_iter=0, tol=-1.0, max_iter=10)
+    with pytest.raises(nn.NNError):
+        nn.invert_batched(P, O, S, 64, fixed_iter=0, tol=float("nan"), max_iter=10)
+    with pytest.raises(ValueError):
+        nn.invert_batched(P, O, S, 64, x0="given", fixed_iter=2)
     with pytest.raises(nn.NNError):
         nn.invert_batched(P.to(torch.complex128), O, S, 64, fixed_iter=4)
+
+
+# ---- tolerance mode: every matrix applies nn_invert's stopping rules -------
+
+def _oracle_tol(G, d, x0, tol, max_iter):
+    ref_dt = np.complex128 if np.iscomplexobj(G) else np.float64
+    return oracle.nn_ref(G.astype(ref_dt), d=d, x0=x0, tol=tol, max_iter=max_iter)
+
+
+def _fixed_bits(P, O, S, iters, d=2, x0="transpose"):
+    X, info = nn.invert_batched(P, O, S, 64, depth=d, x0=x0, fixed_iter=iters)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), nn.decode_batched_info(info)
+
+
+@pytest.mark.parametrize("x0", ["transpose", "identity"])
+def test_tolerance_mode_stops_each_matrix(x0):
+    """Each matrix stops at its own nest count: the result is bitwise the
+    fixed-count result at that count, its rms passed the tolerance, and the
+    count agrees with the oracle's complex128 count to within one nest (the
+    two may stop one nest apart near the tolerance)."""
+    _say(f"tolerance mode mimo 192 x0={x0}")
+    tol, mit = 1e-4, 40
+    packed, offsets, sizes, mats = W.mimo_gram_batch(batch=192, seed=31)
+    P, O, S = _upload(packed, offsets, sizes)
+    X, info = nn.invert_batched(P, O, S, 64, x0=x0, fixed_iter=0, tol=tol, max_iter=mit)
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    it, st, rms = nn.decode_batched_info(info)
+    assert np.all(st == nn.NN_OK), st
+    assert np.all(rms < tol)
+    assert len(set(it.tolist())) >= 3  # the K classes really stop apart
+    x0c = oracle.X0_TRANSPOSE if x0 == "transpose" else oracle.X0_SCALED_IDENTITY
+    for k in sorted(set(it.tolist())):
+        Xf, (itf, stf, rmsf) = _fixed_bits(P, O, S, k, x0=x0)
+        for b in np.nonzero(it == k)[0]:
+            K = int(sizes[b])
+            sl = slice(offsets[b], offsets[b] + K * K)
+            assert np.array_equal(X[sl], Xf[sl]), (b, K, k)
+            assert rms[b] == rmsf[b], (b, rms[b], rmsf[b])
+    for b in range(0, 192, 5):
+        Xo, io = _oracle_tol(mats[b], 2, x0c, tol, mit)
+        assert io["status"] == oracle.OK
+        assert abs(int(it[b]) - io["iters"]) <= 1, (b, it[b], io["iters"])
+        if it[b] == io["iters"]:
+            K = int(sizes[b])
+            Xg = X[offsets[b]:offsets[b] + K * K].reshape(K, K).astype(Xo.dtype)
+            assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < TOL, b
+
+
+def test_tolerance_mode_not_converged_and_stagnated():
+    """tol 0 is unreachable: each matrix ends STAGNATED at its single-precision
+    floor (returning the iterate before the last nest, bitwise the fixed-count
+    result at the reported count) or NOT_CONVERGED at max_iter; a small
+    max_iter gives NOT_CONVERGED with exactly max_iter nests."""
+    _say("tolerance mode floor / max_iter")
+    packed, offsets, sizes, mats = W.ragged_batch([3, 8, 17, 33, 64, 64, 40, 16], seed=41,
+                                                 lo=1.0, hi=50.0)
+    P, O, S = _upload(packed, offsets, sizes)
+    X, info = nn.invert_batched(P, O, S, 64, fixed_iter=0, tol=0.0, max_iter=60)
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    it, st, rms = nn.decode_batched_info(info)
+    assert np.all((st == nn.NN_STAGNATED) | (st == nn.NN_NOT_CONVERGED)), st
+    assert np.any(st == nn.NN_STAGNATED)
+    for b in range(len(mats)):
+        K = int(sizes[b])
+        Xf, (_, _, rmsf) = _fixed_bits(P, O, S, int(it[b]))
+        sl = slice(offsets[b], offsets[b] + K * K)
+        assert np.array_equal(X[sl], Xf[sl]), (b, K, it[b], st[b])
+        assert rms[b] == rmsf[b]
+        # at the floor: within a few single-precision roundings of the exact inverse
+        G = mats[b].astype(np.complex128)
+        Xg = X[sl].reshape(K, K).astype(np.complex128)
+        Xi = np.linalg.inv(G)
+        assert np.linalg.norm(Xg - Xi) / np.linalg.norm(Xi) < 1e-4, b
+    X2, info2 = nn.invert_batched(P, O, S, 64, fixed_iter=0, tol=1e-30, max_iter=2)
+    torch.cuda.synchronize()
+    it2, st2, _ = nn.decode_batched_info(info2)
+    assert np.all(st2 == nn.NN_NOT_CONVERGED) and np.all(it2 == 2)
+    Xf, _ = _fixed_bits(P, O, S, 2)
+    assert np.array_equal(X2.cpu().numpy(), Xf)
+
+
+def test_given_start_continues_the_iteration():
+    """x0='given': X holds X_2 from a fixed 2-nest run; two more nests give
+    bitwise the fixed 4-nest result, and the tolerance mode from X_2 stops
+    where the oracle, started from the same X_2, stops (within one nest)."""
+    _say("given start")
+    packed, offsets, sizes, mats = W.mimo_gram_batch(batch=96, seed=33)
+    P, O, S = _upload(packed, offsets, sizes)
+    X2, _ = nn.invert_batched(P, O, S, 64, fixed_iter=2)
+    X4, _ = nn.invert_batched(P, O, S, 64, fixed_iter=4)
+    Xg = X2.clone()
+    nn.invert_batched(P, O, S, 64, x0="given", fixed_iter=2, X=Xg)
+    torch.cuda.synchronize()
+    assert torch.equal(Xg, X4)
+    Xt = X2.clone()
+    _, info = nn.invert_batched(P, O, S, 64, x0="given", fixed_iter=0, tol=1e-4, max_iter=40,
+                                X=Xt)
+    torch.cuda.synchronize()
+    it, st, rms = nn.decode_batched_info(info)
+    assert np.all(st == nn.NN_OK) and np.all(rms < 1e-4)
+    X2h = X2.cpu().numpy()
+    for b in range(0, 96, 7):
+        K = int(sizes[b])
+        start = X2h[offsets[b]:offsets[b] + K * K].reshape(K, K).astype(np.complex128)
+        _, io = oracle.nn_ref(mats[b].astype(np.complex128), d=2, x0=oracle.X0_GIVEN,
+                              X_init=start, tol=1e-4, max_iter=40)
+        assert io["status"] == oracle.OK
+        assert abs(int(it[b]) - io["iters"]) <= 1, (b, it[b], io["iters"])
+
+
+def test_tolerance_mode_alone_vs_in_mix_bitwise():
+    _say("tolerance mode alone vs mix")
+    packed, offsets, sizes, mats = W.mimo_gram_batch(batch=128, seed=34)
+    X, info = _run(packed, offsets, sizes, 64, fixed_iter=0, tol=1e-5, max_iter=30)
+    it, _, rms = info
+    for b in (0, 9, 64, 127):
+        p1, o1, s1 = W.pack_batch([mats[b]], np.complex64)
+        X1, (it1, _, rms1) = _run(p1, o1, s1, 64, fixed_iter=0, tol=1e-5, max_iter=30)
+        K = mats[b].shape[0]
+        assert np.array_equal(X1, X[offsets[b]:offsets[b] + K * K]), b
+        assert it1[0] == it[b] and rms1[0] == rms[b]
