@@ -395,7 +395,12 @@ nn_status nn_batched_set_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
  *      (Sec. II-D Theorem: X <- X sum_{n=0..d} (I - A X)^n) and the residual
  *      of the new iterate.
  * Requests enqueue on a pool of n_streams streams (default priority), so the
- * GEMMs of small requests run side by side on the device.  Iterates stay in
+ * GEMMs of small requests run side by side on the device.  Single-precision
+ * requests with n <= batch_max_n run their whole single-precision phase in
+ * the tick that admits them: one persistent batched launch per dtype applies
+ * every such request's rules on the device (nn_invert_batched's tolerance
+ * mode from the server's X_0); one that must finish wide stops at the
+ * promotion point, pow(1e-9, 1/(d+1)), and continues tick by tick.  Iterates stay in
  * the pool between ticks.  A request's result depends only on that request:
  * every kernel's tile plan depends on (n, dtype) alone and every reduction
  * runs in a fixed order, so a request gives the same bits alone and in any
@@ -413,7 +418,10 @@ nn_status nn_batched_set_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
  * The server is driven by one host thread (calls are not thread safe).  It
  * allocates no device memory: everything lives in the caller's pool.  It
  * allocates host memory and pinned host memory for the per-tick read-back
- * (16 bytes per active slot) and creates its streams and events.
+ * (16 bytes per active slot, plus about 48 bytes per slot for the batched
+ * launch's arguments and records) and creates its streams and events.  The
+ * head of the pool holds the slots and the batched launch's arrays (about
+ * 64 bytes per max_active slot plus 4 KB).
  * ------------------------------------------------------------------------- */
 
 typedef struct nn_server nn_server;
@@ -426,7 +434,11 @@ typedef struct {
   int32_t n_streams;  /* streams the requests are spread over, 1..8 */
   double wide_tol;    /* tolerances below this finish in FP64 / complex128 */
   int32_t power_k;    /* NN_X0_POWER_*: power steps, 1..NN_POWER_MAX_K */
-  int32_t reserved;   /* ignored; set to 0 */
+  int32_t batch_max_n; /* 0..64: FP32 / complex64 requests with n <= this (and
+                          max_iter <= 4096) run their single-precision phase
+                          in one persistent batched launch per tick and dtype
+                          (the tolerance mode of nn_invert_batched, started
+                          from the server's X_0); 0 turns this off */
 } nn_server_params;
 
 typedef struct {
@@ -454,7 +466,7 @@ typedef struct {
 /* Create a server on ctx's device.  `pool` is a device buffer of pool_bytes
  * (256-byte aligned) owned by the caller and used by the server until
  * nn_server_destroy; params NULL selects {2, NN_X0_SCALED_IDENTITY, 1024, 4,
- * 1e-6, 8, 0}. */
+ * 1e-6, 8, 64}. */
 nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
                            const nn_server_params* params, nn_server** server);
 

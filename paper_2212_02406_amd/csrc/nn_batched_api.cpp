@@ -169,6 +169,19 @@ BatchedGraph make_key(nn_ctx* ctx, const void* A, void* X, const int64_t* offset
 }
 
 }  // namespace
+
+// Uncaptured launch for callers whose arguments change on every call.  The
+// configuration is the context's entry for (dtype, 64) whatever the batch's
+// largest size, so a matrix's path (one wave or a group) depends on its own
+// size only; the arithmetic is the same on either path.
+hipError_t launch_batched_direct(nn_ctx* ctx, BatchedArgs a, hipStream_t s) {
+  const BatchedTune t = lookup(ctx, a.dt, 64);
+  a.wave_max_k = std::min({t.wave_max_k, a.max_n, 32});
+  const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(a.dt, a.max_n, a.wave_max_k, a.depth));
+  a.grid = std::max(1, std::min(a.batch, ctx->num_cus * per_cu));
+  return launch_batched(a, s);
+}
+
 }  // namespace nn
 
 using namespace nn;

@@ -214,6 +214,10 @@ struct BatchedGraph {
   int max_iter = 0;
 };
 
+// Uncaptured batched launch with the configuration of ctx's table for
+// (a.dt, 64); fills a.wave_max_k and a.grid (nn_batched_api.cpp).
+hipError_t launch_batched_direct(nn_ctx* ctx, BatchedArgs a, hipStream_t s);
+
 }  // namespace nn
 
 constexpr int kTimedGemms = 1024;

@@ -23,6 +23,16 @@
 // The promotion point is one narrow nest past the rms at which the next nest
 // of order d+1 would reach about 1e-9: the narrow iterate then sits at its
 // rounding floor, and one or two wide nests finish it.
+//
+// Small requests (FP32 / complex64, n <= batch_max_n <= 64) skip the per-nest
+// ticks of their narrow phase: the tick that admits them forms their X_0 like
+// any other request's, then runs all of them, one launch per dtype, through
+// the batched persistent kernel in its tolerance mode (each matrix applies the
+// rules above on the device, with X, R and U in LDS).  A request that must
+// finish wide stops there at the promotion point instead of its tolerance and
+// is promoted; a stagnated one is promoted if the wide buffers fit.  The
+// batched kernel's result does not depend on the rest of the batch, so the
+// co-runner independence of results holds for this path too.
 #include <math.h>
 #include <string.h>
 
@@ -46,6 +56,7 @@ constexpr int kMaxStreams = 8;
 constexpr int kMaxActiveLimit = 65536;
 constexpr int kMaxBypassTicks = 8;
 constexpr int kBypassScan = 64;
+constexpr int kBatchMaxN = 64;  // the batched kernel's largest size
 
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -129,6 +140,8 @@ struct Request {
   int slot = -1;
   int stream = 0;
   bool fresh = false;  // admitted this tick: den not checked yet
+  bool small = false;  // narrow phase in this tick's batched launch
+  int bidx = -1;       // its index in that launch's arrays
   bool polled = false;   // its record has been handed out by nn_server_poll
   bool dropped = false;  // fetched or released before it was polled
   int cur = 0;         // X[cur] is the current iterate
@@ -185,6 +198,13 @@ struct nn_server {
   hipEvent_t done[kMaxStreams] = {};
   hipStream_t ctl = nullptr;
   hipEvent_t entry = nullptr;  // orders the server's streams after the context stream
+  // Batched narrow phase: argument arrays (max_active entries each) and the
+  // plan workspace after the slots; pinned staging of the arrays (same
+  // layout) followed by the per-matrix records read back.
+  char* bdev = nullptr;
+  char* bhost = nullptr;
+  size_t barg_bytes = 0;
+  std::vector<Request*> small_new;  // admitted this tick, small path
   int rr = 0;
   std::chrono::steady_clock::time_point t0;
 
@@ -201,6 +221,29 @@ namespace {
     hipError_t e_ = (expr);                   \
     if (e_ != hipSuccess) return NN_ERR_HIP; \
   } while (0)
+
+// Layout of the batched argument block for m entries (device and host).
+struct BatchLayout {
+  size_t off, xoff, tols, sizes, maxits, bytes;  // argument arrays
+  size_t info, ws, total;                         // device: + records, plan workspace
+};
+BatchLayout batch_layout(int m) {
+  BatchLayout L;
+  L.off = 0;
+  L.xoff = L.off + up(8 * (size_t)m);
+  L.tols = L.xoff + up(8 * (size_t)m);
+  L.sizes = L.tols + up(8 * (size_t)m);
+  L.maxits = L.sizes + up(4 * (size_t)m);
+  L.bytes = L.maxits + up(4 * (size_t)m);
+  L.info = L.bytes;
+  L.ws = L.info + up(sizeof(nn_info_dev) * (size_t)m);
+  L.total = L.ws + up(batched_ws_bytes(m));
+  return L;
+}
+
+bool small_path(const nn_server* s, int64_t n, nn_dtype dt, int32_t max_iter) {
+  return single_dtype(dt) && n <= s->prm.batch_max_n && max_iter <= kBatchedMaxIter;
+}
 
 size_t footprint_of(const nn_server* s, int64_t n, nn_dtype dt, double tol, bool* reserve_wide) {
   const int d = s->prm.depth;
@@ -284,7 +327,8 @@ hipError_t enqueue_nest(nn_server* s, Request* q) {
   return launch_gemm(e, cplx, plan, g, st);
 }
 
-// Copy A into the pool, form den and X_0, copy den to the slot, residual.
+// Copy A into the pool, form den and X_0, copy den to the slot, then the
+// residual (not for the small path, whose residuals run in the batched launch).
 hipError_t enqueue_start(nn_server* s, Request* q) {
   hipStream_t st = s->streams[q->stream];
   const PhaseBufs& P = q->ph[q->cur_ph];
@@ -299,7 +343,7 @@ hipError_t enqueue_start(nn_server* s, Request* q) {
                        hipMemcpyDeviceToDevice, st);
   if (err != hipSuccess) return err;
   q->cur = 0;
-  return enqueue_residual(s, q);
+  return q->small ? hipSuccess : enqueue_residual(s, q);
 }
 
 // Widen A and the iterate X[from] into the wide phase, then its residual.
@@ -376,11 +420,105 @@ nn_status admit(nn_server* s) {
     q->stream = s->rr++ % s->n_streams;
     q->state = State::Active;
     q->fresh = true;
+    q->small = small_path(s, q->n, q->dt, q->max_iter);
     q->t_admit = s->now();
     HIP_TRY(enqueue_start(s, q));
+    if (q->small) s->small_new.push_back(q);
     s->active.push_back(q);
     it = s->queued.erase(it);
   }
+  return NN_OK;
+}
+
+// One batched launch per dtype over the requests admitted to the small path
+// this tick, after their starts (on every stream) and before the tick's
+// read-back, which then holds their records.  A request that finishes wide
+// stops at the promotion point.
+nn_status launch_small(nn_server* s) {
+  if (s->small_new.empty()) return NN_OK;
+  hipStream_t st = s->streams[0];
+  for (int i = 1; i < s->n_streams; ++i) {
+    HIP_TRY(hipEventRecord(s->done[i], s->streams[i]));
+    HIP_TRY(hipStreamWaitEvent(st, s->done[i], 0));
+  }
+  const int m = s->prm.max_active;
+  const BatchLayout L = batch_layout(m);
+  int64_t* off = reinterpret_cast<int64_t*>(s->bhost + L.off);
+  int64_t* xoff = reinterpret_cast<int64_t*>(s->bhost + L.xoff);
+  double* tols = reinterpret_cast<double*>(s->bhost + L.tols);
+  int32_t* sizes = reinterpret_cast<int32_t*>(s->bhost + L.sizes);
+  int32_t* maxits = reinterpret_cast<int32_t*>(s->bhost + L.maxits);
+  const double point = pow(1e-9, 1.0 / (s->prm.depth + 1));
+  int j = 0;
+  int first[2] = {0, 0}, count[2] = {0, 0}, maxn[2] = {0, 0};
+  const nn_dtype dts[2] = {NN_F32, NN_C64};
+  for (int g = 0; g < 2; ++g) {
+    first[g] = j;
+    for (Request* q : s->small_new) {
+      if (q->dt != dts[g]) continue;
+      const PhaseBufs& P = q->ph[0];
+      const size_t e = elem_size(q->dt);
+      q->bidx = j;
+      off[j] = (int64_t)((static_cast<char*>(P.A) - s->pool) / e);
+      xoff[j] = (int64_t)((static_cast<char*>(P.X[0]) - s->pool) / e);
+      sizes[j] = (int32_t)q->n;
+      tols[j] = q->reserve_wide ? std::max(q->tol, point) : q->tol;
+      maxits[j] = q->max_iter;
+      maxn[g] = std::max(maxn[g], (int)q->n);
+      ++j;
+    }
+    count[g] = j - first[g];
+  }
+  HIP_TRY(hipMemcpyAsync(s->bdev, s->bhost, L.bytes, hipMemcpyHostToDevice, st));
+  nn_info_dev* info = reinterpret_cast<nn_info_dev*>(s->bdev + L.info);
+  for (int g = 0; g < 2; ++g) {
+    if (!count[g]) continue;
+    const int f = first[g];
+    BatchedArgs a;
+    a.dt = dts[g];
+    a.A = s->pool;
+    a.X = s->pool;
+    a.offsets = reinterpret_cast<const int64_t*>(s->bdev + L.off) + f;
+    a.xoffsets = reinterpret_cast<const int64_t*>(s->bdev + L.xoff) + f;
+    a.sizes = reinterpret_cast<const int32_t*>(s->bdev + L.sizes) + f;
+    a.tols = reinterpret_cast<const double*>(s->bdev + L.tols) + f;
+    a.maxits = reinterpret_cast<const int32_t*>(s->bdev + L.maxits) + f;
+    a.batch = count[g];
+    a.max_n = maxn[g];
+    a.depth = s->prm.depth;
+    a.x0 = NN_X0_GIVEN;
+    a.iters = 0;
+    a.ws = s->bdev + L.ws;
+    a.info = info + f;
+    HIP_TRY(launch_batched_direct(s->ctx, a, st));
+  }
+  HIP_TRY(hipMemcpyAsync(s->bhost + L.info, info, sizeof(nn_info_dev) * (size_t)j,
+                         hipMemcpyDeviceToHost, st));
+  s->small_new.clear();
+  return NN_OK;
+}
+
+// The batched narrow phase's record of a small request: retire it, or
+// promote it to the wide phase (which continues tick by tick).
+nn_status step_small(nn_server* s, Request* q, bool* keep) {
+  const BatchLayout L = batch_layout(s->prm.max_active);
+  const nn_info_dev r = reinterpret_cast<const nn_info_dev*>(s->bhost + L.info)[q->bidx];
+  q->small = false;
+  q->bidx = -1;
+  q->iters = r.iters;
+  q->phase_k = r.iters;
+  q->cur = 0;  // the batched launch leaves its result in X[0]
+  *keep = false;
+  const bool ok_narrow = r.status == NN_OK && r.rms < q->tol;
+  const bool promote = (r.status == NN_OK && !ok_narrow) || r.status == NN_STAGNATED;
+  if (promote && reserve_wide_late(s, q)) {
+    HIP_TRY(enqueue_promote(s, q, 0));
+    *keep = true;
+    return NN_OK;
+  }
+  // OK, or a stagnation that cannot be promoted (the OK-above-tolerance case
+  // always has its wide buffers, reserved at admission).
+  retire(s, q, r.status, r.rms, 0);
   return NN_OK;
 }
 
@@ -393,10 +531,12 @@ nn_status step_request(nn_server* s, Request* q, bool* keep) {
     q->fresh = false;
     const double den = h[1];
     if (!isfinite(den) || den <= 0.0) {
+      q->small = false;
       retire(s, q, isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE, NAN, q->cur);
       return NN_OK;
     }
   }
+  if (q->small) return step_small(s, q, keep);
   const double rms = h[0];
   const bool narrow = q->cur_ph == 0;
   const double sqn = sqrt((double)q->n);
@@ -486,7 +626,7 @@ extern "C" {
 nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
                            const nn_server_params* params, nn_server** out) {
   if (!ctx || !pool || !out) return NN_ERR_ARG;
-  nn_server_params p{2, NN_X0_SCALED_IDENTITY, 1024, 4, 1e-6, 8, 0};
+  nn_server_params p{2, NN_X0_SCALED_IDENTITY, 1024, 4, 1e-6, 8, kBatchMaxN};
   if (params) p = *params;
   if (p.depth < 1 || p.depth > NN_MAX_DEPTH) return NN_ERR_ARG;
   if (p.x0 < NN_X0_TRANSPOSE || p.x0 > NN_X0_JACOBI || p.x0 == NN_X0_GIVEN) return NN_ERR_ARG;
@@ -496,7 +636,10 @@ nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
   if (p.max_active < 1 || p.max_active > kMaxActiveLimit) return NN_ERR_ARG;
   if (p.n_streams < 1 || p.n_streams > kMaxStreams) return NN_ERR_ARG;
   if (!(p.wide_tol >= 0.0)) return NN_ERR_ARG;
-  const size_t head = up(2 * sizeof(double) * (size_t)p.max_active);
+  if (p.batch_max_n < 0 || p.batch_max_n > kBatchMaxN) return NN_ERR_ARG;
+  const size_t slots = up(2 * sizeof(double) * (size_t)p.max_active);
+  const BatchLayout L = batch_layout(p.max_active);
+  const size_t head = slots + L.total;
   if ((reinterpret_cast<uintptr_t>(pool) & (kAlign - 1)) || pool_bytes <= head)
     return NN_ERR_WORKSPACE;
   nn_server* s = new (std::nothrow) nn_server();
@@ -505,6 +648,7 @@ nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
   s->prm = p;
   s->n_streams = p.n_streams;
   s->slots_dev = static_cast<double*>(pool);
+  s->bdev = static_cast<char*>(pool) + slots;
   s->pool = static_cast<char*>(pool) + head;
   s->pool_bytes = (pool_bytes - head) / kAlign * kAlign;
   s->alloc.reset(s->pool_bytes);
@@ -514,8 +658,11 @@ nn_status nn_server_create(nn_ctx* ctx, void* pool, size_t pool_bytes,
             hipHostMalloc(reinterpret_cast<void**>(&s->slots_host),
                           2 * sizeof(double) * (size_t)p.max_active, hipHostMallocDefault) ==
                 hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&s->bhost), L.ws, hipHostMallocDefault) ==
+                hipSuccess &&
             hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&s->entry, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&s->entry, hipEventDisableTiming) == hipSuccess &&
+            (p.batch_max_n == 0 || batched_allow_lds() == hipSuccess);
   for (int i = 0; ok && i < s->n_streams; ++i)
     ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming) == hipSuccess;
@@ -543,6 +690,7 @@ void nn_server_destroy(nn_server* s) {
   }
   if (s->entry) (void)hipEventDestroy(s->entry);
   if (s->slots_host) (void)hipHostFree(s->slots_host);
+  if (s->bhost) (void)hipHostFree(s->bhost);
   std::vector<Request*> all;
   for (auto& kv : s->by_id) all.push_back(kv.second);
   for (Request* q : s->unpolled)
@@ -584,6 +732,8 @@ nn_status nn_server_tick(nn_server* s, nn_server_stats* stats) {
   HIP_TRY(hipEventRecord(s->entry, s->ctx->stream));
   for (int i = 0; i < s->n_streams; ++i) HIP_TRY(hipStreamWaitEvent(s->streams[i], s->entry, 0));
   nn_status st = admit(s);
+  if (st != NN_OK) return st;
+  st = launch_small(s);
   if (st != NN_OK) return st;
   if (s->active.empty()) {
     fill_stats(s, 0, stats);

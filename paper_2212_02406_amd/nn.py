@@ -84,7 +84,7 @@ class nn_info_dev(ctypes.Structure):
 class nn_server_params(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("x0", ctypes.c_int32), ("max_active", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("wide_tol", ctypes.c_double),
-                ("power_k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("power_k", ctypes.c_int32), ("batch_max_n", ctypes.c_int32)]
 
 
 class nn_request_info(ctypes.Structure):
@@ -567,7 +567,8 @@ class Server:
     """
 
     def __init__(self, pool_bytes, depth=2, x0="identity", max_active=1024, n_streams=4,
-                 wide_tol=1e-6, device=0, ctx: Context | None = None, power_k=8):
+                 wide_tol=1e-6, device=0, ctx: Context | None = None, power_k=8,
+                 batch_max_n=64):
         torch = _torch()
         self.ctx = ctx or default_context(device)
         self.device = torch.device("cuda", device)
@@ -575,7 +576,7 @@ class Server:
         p = nn_server_params()
         p.depth, p.x0 = int(depth), X0_NAMES[x0] if isinstance(x0, str) else int(x0)
         p.max_active, p.n_streams, p.wide_tol = int(max_active), int(n_streams), float(wide_tol)
-        p.power_k, p.reserved = int(power_k), 0
+        p.power_k, p.batch_max_n = int(power_k), int(batch_max_n)
         self.params = p
         self._ptr = ctypes.c_void_p()
         st = nn_server_create(self.ctx.ptr, ctypes.c_void_p(self._pool[1]), self._pool[2],

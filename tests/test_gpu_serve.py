@@ -16,6 +16,9 @@ Parity bars:
   FP32-formed rms is within 1e-6 absolute of the true one, so the true rms is
   below tol + 1e-6.
 * Alone vs in a mix: bitwise identical X, iterations and status.
+* Small path (single precision, n <= batch_max_n): the request's narrow phase
+  is nn_invert_batched's tolerance mode started from the server's X_0, so its
+  result, nest count and rms equal that call's bit for bit.
 """
 import sys
 
@@ -114,7 +117,7 @@ def test_single_precision_results_equal_nn_invert(x0):
                 for i, (n, _, cx) in enumerate(CASES)]
     else:
         reqs = [(i, _mat(n, c, 100 + i, cx), 1e-4, 100) for i, (n, c, cx) in enumerate(CASES)]
-    res = _serve(reqs, x0=x0)
+    res = _serve(reqs, x0=x0, batch_max_n=0)  # every request through the per-tick nests
     for rid, A, tol, _ in reqs:
         rec, X = res[rid]
         assert rec["status"] == nn.NN_OK and rec["wide_iters"] == 0, rec
@@ -207,8 +210,13 @@ def test_small_requests_pass_a_large_one_that_does_not_fit():
     for i, A in enumerate(dv):
         srv.submit(i, A, 1e-4, 100)
     s = srv.tick()
-    assert s.active == 5 and s.queued == 1  # big[1] waits, the small ones pass it
-    recs = []
+    # big[1] waits, the small ones pass it (and, on the batched small path,
+    # finish in this tick)
+    assert s.active + s.finished == 5 and s.queued == 1
+    recs = [r for r in srv.poll()]
+    for r in recs:
+        assert r["status"] == nn.NN_OK
+        srv.release(r["id"])
     for _ in range(1000):  # results are released as they retire, freeing the pool
         s = srv.tick()
         for r in srv.poll():
@@ -239,8 +247,9 @@ def test_host_source_equals_device_source():
     assert np.array_equal(X1, X2)
 
 
-def test_statuses_match_oracle_rules():
-    _say("serve statuses")
+@pytest.mark.parametrize("batch_max_n", [0, 64])
+def test_statuses_match_oracle_rules(batch_max_n):
+    _say(f"serve statuses batch_max_n={batch_max_n}")
     n = 64
     neg = -np.eye(n, dtype=np.float32)
     nan = _mat(n, 10.0, 700, False)
@@ -248,7 +257,7 @@ def test_statuses_match_oracle_rules():
     slow = _mat(n, 1e3, 701, False)
     floor = _mat(n, 1e3, 702, True)
     reqs = [(0, neg, 1e-4, 100), (1, nan, 1e-4, 100), (2, slow, 1e-4, 2), (3, floor, 0.0, 100)]
-    res = _serve(reqs)
+    res = _serve(reqs, batch_max_n=batch_max_n)
     assert res[0][0]["status"] == nn.NN_ERR_DIVERGED and res[0][0]["iters"] == 0
     assert res[1][0]["status"] == nn.NN_ERR_NONFINITE
     assert res[2][0]["status"] == nn.NN_NOT_CONVERGED and res[2][0]["iters"] == 2
@@ -288,3 +297,69 @@ def test_argument_errors():
     with pytest.raises(nn.NNError):
         srv.release(5)
     srv.close()
+
+
+SMALL = [(1, 1.0, False), (5, 10.0, True), (16, 100.0, False), (33, 1e3, True), (48, 50.0, False),
+         (64, 1e3, True), (64, 20.0, False), (17, 5.0, True)]
+
+
+def _start_iterate(A, x0):
+    """The X_0 the server forms (nn_invert stops at k = 0 under a huge tolerance)."""
+    X0, info = nn.invert(_dev(A), depth=2, x0=x0, tol=1e30, max_iter=1)
+    assert info["iters"] == 0 and info["status"] == nn.NN_OK
+    return X0
+
+
+@pytest.mark.parametrize("x0", ["identity", "power_identity", "transpose"])
+def test_small_path_equals_batched_tolerance_mode(x0):
+    """Small single-precision requests retire in the tick that admits them,
+    bit for bit as nn_invert_batched's tolerance mode from the same X_0."""
+    _say(f"serve small path x0={x0}")
+    reqs = [(i, _mat(n, c, 900 + i, cx), 1e-4, 100) for i, (n, c, cx) in enumerate(SMALL)]
+    srv = nn.Server(256 * MB, x0=x0)
+    devs = {rid: _dev(A) for rid, A, _, _ in reqs}
+    torch.cuda.synchronize()
+    for rid, A, tol, mi in reqs:
+        srv.submit(rid, devs[rid], tol, mi)
+    st = srv.tick()
+    assert st.finished == len(reqs) and st.active == 0
+    recs = {r["id"]: r for r in srv.poll()}
+    for rid, A, tol, _ in reqs:
+        rec = recs[rid]
+        X = srv.fetch(rid, rec["n"], rec["out_dtype"], out_device="cpu").numpy()
+        assert rec["status"] == nn.NN_OK and rec["wide_iters"] == 0, rec
+        n = A.shape[0]
+        p, o, sz = W.pack_batch([A], A.dtype)
+        P, O, S = _dev(p), _dev(o), _dev(sz)
+        Xb = _start_iterate(A, x0).reshape(-1).clone()
+        _, info = nn.invert_batched(P, O, S, 64, x0="given", X=Xb, fixed_iter=0, tol=tol,
+                                    max_iter=100)
+        torch.cuda.synchronize()
+        it, stb, rms = nn.decode_batched_info(info)
+        assert stb[0] == nn.NN_OK and it[0] == rec["iters"] and rms[0] == rec["rms"], (rec, it, rms)
+        assert np.array_equal(Xb.cpu().numpy(), X.reshape(-1)), rid
+        if x0 == "identity":
+            _check_vs_oracle(A, rec, X, tol)
+    srv.close()
+
+
+def test_small_path_wide_finish_matches_oracle():
+    """tol 1e-8: the batched phase stops at the promotion point and the wide
+    phase finishes; results against the oracle, and alone vs in a mix."""
+    _say("serve small path tol 1e-8")
+    reqs = [(i, _mat(n, c, 950 + i, cx), 1e-8, 100) for i, (n, c, cx) in enumerate(SMALL)]
+    res = _serve(reqs)
+    for rid, A, tol, _ in reqs:
+        rec, X = res[rid]
+        assert rec["status"] == nn.NN_OK, rec
+        if A.shape[0] > 1:  # n = 1: X_0 = 1/a is exact (rms 0) and finishes narrow
+            assert rec["wide_iters"] > 0, rec
+            assert X.dtype == (np.complex128 if np.iscomplexobj(A) else np.float64)
+        _check_vs_oracle(A, rec, X, tol)
+    mix = _serve(reqs + [(100, _mat(300, 100.0, 990, True), 1e-8, 100)], stagger=2)
+    for rid, A, tol, _ in reqs:
+        ra, Xa = res[rid]
+        rm, Xm = mix[rid]
+        for k in ("status", "iters", "wide_iters", "out_dtype", "rms"):
+            assert ra[k] == rm[k], (k, ra, rm)
+        assert np.array_equal(Xa, Xm), rid
