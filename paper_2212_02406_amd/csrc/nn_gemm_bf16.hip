@@ -12,8 +12,13 @@
 //
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l supplies A[l%16][8(l/16) .. +7] and
 // Bt[l%16][8(l/16) .. +7] (16 bytes each) and returns rows 4 (l/16) + t of
-// column l%16 (measured on gfx950).  Tile 128 x 128 x 64, 4 waves of 64 x 64,
-// two LDS buffers, XCD-aware tile order as in the FP64/FP32 kernel.
+// column l%16 (measured on gfx950).  Two tilings: 128 x 128 x 64 with 4 waves
+// of 64 x 64 (any shape), and 256 x 256 x 64 with 8 waves of 128 x 64 for large
+// products (half the LDS fragment reads per MFMA: a wave reads 8 + 4 fragments
+// for 32 MFMAs instead of 4 + 4 for 16).  Both use two LDS buffers and the
+// XCD-aware tile order of the FP64/FP32 kernel.  Every output element is
+// accumulated over the same k in the same order by the same instruction in
+// both tilings, so C is the same bits; only the per-tile partials differ.
 #include <stdlib.h>
 
 #include "nn_internal.h"
@@ -25,7 +30,7 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, BK = 64, NT = 256;
+constexpr int BK = 64;
 constexpr int LDS_STRIDE = BK + 8;  // bf16 elements; 144-byte rows: conflict-free 16-byte reads
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -50,15 +55,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
   return x * q + (x < r ? x : r) + local;
 }
 
-// EXACT: M, N multiples of 128 and K of 64 (no bounds checks anywhere).
-template <bool EXACT>
-__global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDS_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDS_STRIDE];
-  __shared__ double red[4];
+// Tile TBM x TBN x 64 over WGM x WGN waves.  EXACT: M, N multiples of the
+// tile and K of 64 (no bounds checks anywhere).
+template <int TBM, int TBN, int WGM, int WGN, bool EXACT>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+    gemm_bf16_kernel(Bf16GemmArgs p, int tiles_m, int tiles_n) {
+  constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+  constexpr int FI = TBM / WGM / 16, FJ = TBN / WGN / 16;  // 16 x 16 blocks per wave
+  constexpr int VA = TBM * BK / 8 / NT, VB = TBN * BK / 8 / NT;  // 16-byte vectors per thread
+  constexpr int RS = NT / 8;  // slab rows per staging pass
+  static_assert(VA * NT * 8 == TBM * BK && VB * NT * 8 == TBN * BK, "staging must tile the slab");
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][TBM * LDS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TBN * LDS_STRIDE];
+  __shared__ double red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   // tile order: XCD-contiguous ranges, 8 tile-rows per group
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int group = 8 * tiles_n;
@@ -66,76 +78,78 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
   const int gsize = (tiles_m - first) < 8 ? (tiles_m - first) : 8;
   const int in = tile - gid * group;
   const int pm = first + in % gsize, pn = in / gsize;
-  const int64_t m0 = (int64_t)pm * BM, n0 = (int64_t)pn * BN;
+  const int64_t m0 = (int64_t)pm * TBM, n0 = (int64_t)pn * TBN;
   const uint16_t* __restrict__ A = p.A;
   const uint16_t* __restrict__ Bt = p.Bt;
 
-  f4_t acc[4][4];
+  f4_t acc[FI][FJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{};
+    for (int j = 0; j < FJ; ++j) acc[i][j] = f4_t{};
 
-  // 128 rows x 64 k per operand and slab = 1024 16-byte vectors, 4 per thread
-  u4_t ra[4], rb[4];
+  // TBM (TBN) rows x 64 k per operand and slab in 16-byte vectors, VA (VB) per thread
+  u4_t ra[VA], rb[VB];
   const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZeroBf16);
   // exact tiling: wave-uniform slab base plus a fixed 32-bit offset per load
-  const int r0 = tid >> 3, c0 = (tid & 7) * 8;  // row r0 + 32 i of the slab
+  const int r0 = tid >> 3, c0 = (tid & 7) * 8;  // row r0 + RS i of the slab
   const uint32_t oa = (uint32_t)(r0 * p.lda + c0), ob = (uint32_t)(r0 * p.ldb + c0);
-  const uint32_t sa32 = (uint32_t)(32 * p.lda), sb32 = (uint32_t)(32 * p.ldb);
+  const uint32_t sa32 = (uint32_t)(RS * p.lda), sb32 = (uint32_t)(RS * p.ldb);
   auto gload = [&](int64_t k0) {
     if constexpr (EXACT) {
       const uint16_t* a0 = A + m0 * p.lda + k0;
       const uint16_t* b0 = Bt + n0 * p.ldb + k0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < VA; ++i)
         ra[i] = load_global(reinterpret_cast<uintptr_t>(a0 + (oa + i * sa32)));
-        rb[i] = load_global(reinterpret_cast<uintptr_t>(b0 + (ob + i * sb32)));
-      }
-    } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int v = tid + i * NT;
-        const int r = v >> 3, c = (v & 7) * 8;
-        const int64_t gk = k0 + c;
-        const int64_t ga = m0 + r, gb = n0 + r;
+      for (int i = 0; i < VB; ++i)
+        rb[i] = load_global(reinterpret_cast<uintptr_t>(b0 + (ob + i * sb32)));
+    } else {
+      const int64_t gk = k0 + c0;
+#pragma unroll
+      for (int i = 0; i < VA; ++i) {
+        const int64_t ga = m0 + r0 + i * RS;
         const uintptr_t sa = reinterpret_cast<uintptr_t>(A + ga * p.lda + gk);
-        const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
         ra[i] = load_global((ga < p.M && gk < p.K) ? sa : zaddr);
+      }
+#pragma unroll
+      for (int i = 0; i < VB; ++i) {
+        const int64_t gb = n0 + r0 + i * RS;
+        const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
         rb[i] = load_global((gb < p.N && gk < p.K) ? sb : zaddr);
       }
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int v = tid + i * NT;
-      const int r = v >> 3, c = (v & 7) * 8;
-      *reinterpret_cast<u4_t*>(&As[buf][r * LDS_STRIDE + c]) = ra[i];
-      *reinterpret_cast<u4_t*>(&Bs[buf][r * LDS_STRIDE + c]) = rb[i];
-    }
+    for (int i = 0; i < VA; ++i)
+      *reinterpret_cast<u4_t*>(&As[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < VB; ++i)
+      *reinterpret_cast<u4_t*>(&Bs[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = rb[i];
   };
   const int lr = lane & 15, lk = lane >> 4;
   auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK / 32; ++kk) {
-      bf16x8_t af[4], bf[4];
+      bf16x8_t af[FI], bf[FJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < FI; ++i) {
         const u4_t x = *reinterpret_cast<const u4_t*>(
-            &As[buf][(wm * 64 + i * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
+            &As[buf][(wm * (16 * FI) + i * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
         af[i] = __builtin_bit_cast(bf16x8_t, x);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FJ; ++j) {
         const u4_t x = *reinterpret_cast<const u4_t*>(
-            &Bs[buf][(wn * 64 + j * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
+            &Bs[buf][(wn * (16 * FJ) + j * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
         bf[j] = __builtin_bit_cast(bf16x8_t, x);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   };
@@ -158,12 +172,12 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
   double ss = 0.0;
   const float alpha = (float)p.alpha, diag = (float)p.diag;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < FI; ++i) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t c = n0 + wn * 64 + j * 16 + lr;
+    for (int j = 0; j < FJ; ++j) {
+      const int64_t c = n0 + wn * (16 * FJ) + j * 16 + lr;
       uint16_t tb[4];
-      const int64_t rbase = m0 + wm * 64 + i * 16 + 4 * lk;
+      const int64_t rbase = m0 + wm * (16 * FI) + i * 16 + 4 * lk;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t r = rbase + t;
@@ -191,7 +205,12 @@ __global__ void __launch_bounds__(NT) gemm_bf16_kernel(Bf16GemmArgs p, int tiles
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) p.partials[pm * tiles_n + pn] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) t += red[w];
+      p.partials[pm * tiles_n + pn] = t;
+    }
   }
 }
 
@@ -222,23 +241,44 @@ __global__ void __launch_bounds__(256) cast_bf16_kernel(const S* src, int64_t ld
 
 }  // namespace
 
+// The 256 x 256 tiling when it still gives every CU a tile (>= 256 tiles),
+// else 128 x 128.  NN_BF16_TILE=128 or 256 forces one (read at each call).
 GemmPlan plan_gemm_bf16(int64_t M, int64_t N) {
   GemmPlan p;
-  p.tile = Tile::T128;
-  p.tiles_m = (int)((M + BM - 1) / BM);
-  p.tiles_n = (int)((N + BN - 1) / BN);
+  const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
+  bool use_big = big >= 256;
+  if (const char* v = getenv("NN_BF16_TILE")) {
+    if (atoi(v) == 128) use_big = false;
+    if (atoi(v) == 256) use_big = true;
+  }
+  p.tile = use_big ? Tile::T256 : Tile::T128;
+  const int t = use_big ? 256 : 128;
+  p.tiles_m = (int)((M + t - 1) / t);
+  p.tiles_n = (int)((N + t - 1) / t);
   return p;
 }
 
 hipError_t launch_gemm_bf16(const GemmPlan& plan, const Bf16GemmArgs& a, hipStream_t s) {
   const int grid = plan.num_tiles();
   if (grid <= 0) return hipSuccess;
-  if (a.M % BM == 0 && a.N % BN == 0 && a.K % BK == 0)
-    hipLaunchKernelGGL(gemm_bf16_kernel<true>, dim3(grid), dim3(NT), 0, s, a, plan.tiles_m,
-                       plan.tiles_n);
-  else
-    hipLaunchKernelGGL(gemm_bf16_kernel<false>, dim3(grid), dim3(NT), 0, s, a, plan.tiles_m,
-                       plan.tiles_n);
+  const int tm = plan.tile == Tile::T256 ? 256 : 128;
+  if ((a.M + tm - 1) / tm != plan.tiles_m || (a.N + tm - 1) / tm != plan.tiles_n)
+    return hipErrorInvalidValue;  // the plan was made for another shape
+  const bool exact = a.M % tm == 0 && a.N % tm == 0 && a.K % BK == 0;
+  if (tm == 256) {
+    if (exact)
+      hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 2, 4, true>), dim3(grid), dim3(512), 0, s, a,
+                         plan.tiles_m, plan.tiles_n);
+    else
+      hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 2, 4, false>), dim3(grid), dim3(512), 0, s,
+                         a, plan.tiles_m, plan.tiles_n);
+  } else if (exact) {
+    hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 2, 2, true>), dim3(grid), dim3(256), 0, s, a,
+                       plan.tiles_m, plan.tiles_n);
+  } else {
+    hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 2, 2, false>), dim3(grid), dim3(256), 0, s, a,
+                       plan.tiles_m, plan.tiles_n);
+  }
   return hipGetLastError();
 }
 
