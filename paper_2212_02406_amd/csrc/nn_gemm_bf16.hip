@@ -14,11 +14,14 @@
 // Bt[l%16][8(l/16) .. +7] (16 bytes each) and returns rows 4 (l/16) + t of
 // column l%16 (measured on gfx950).  Two tilings: 128 x 128 x 64 with 4 waves
 // of 64 x 64 (any shape), and 256 x 256 x 64 with 8 waves of 128 x 64 for large
-// products (half the LDS fragment reads per MFMA: a wave reads 8 + 4 fragments
-// for 32 MFMAs instead of 4 + 4 for 16).  Both use two LDS buffers and the
-// XCD-aware tile order of the FP64/FP32 kernel.  Every output element is
-// accumulated over the same k in the same order by the same instruction in
-// both tilings, so C is the same bits; only the per-tile partials differ.
+// products (a wave reads 8 + 4 fragments for 32 MFMAs instead of 4 + 4 for 16).
+// Both use two LDS buffers and the XCD-aware tile order of the FP64/FP32
+// kernel.  For exact tilings the operands are loaded straight into
+// LDS (global_load_lds_dwordx4: lane l of a wave writes bytes 16 l .. 16 l + 15
+// of a 1 KB block, measured on gfx950) into XOR-swizzled rows, which frees
+// the staging registers and the LDS store instructions.  Every output element
+// is accumulated over the same k in the same order by the same instruction in
+// all forms, so C is the same bits; only the per-tile partials differ.
 #include <stdlib.h>
 
 #include "nn_internal.h"
@@ -56,8 +59,10 @@ __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
 }
 
 // Tile TBM x TBN x 64 over WGM x WGN waves.  EXACT: M, N multiples of the
-// tile and K of 64 (no bounds checks anywhere).
-template <int TBM, int TBN, int WGM, int WGN, bool EXACT>
+// tile and K of 64 (no bounds checks anywhere).  DMA (exact tilings only):
+// the operands go from global memory straight into LDS, 16 bytes per lane
+// (global_load_lds_dwordx4), instead of through registers; see the loop.
+template <int TBM, int TBN, int WGM, int WGN, bool EXACT, bool DMA = false>
 __global__ void __launch_bounds__(64 * WGM * WGN)
     gemm_bf16_kernel(Bf16GemmArgs p, int tiles_m, int tiles_n) {
   constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
@@ -65,8 +70,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
   constexpr int VA = TBM * BK / 8 / NT, VB = TBN * BK / 8 / NT;  // 16-byte vectors per thread
   constexpr int RS = NT / 8;  // slab rows per staging pass
   static_assert(VA * NT * 8 == TBM * BK && VB * NT * 8 == TBN * BK, "staging must tile the slab");
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][TBM * LDS_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TBN * LDS_STRIDE];
+  static_assert(!DMA || (EXACT && TBM % (8 * NW) == 0 && TBN % (8 * NW) == 0), "DMA form: exact");
   __shared__ double red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -88,86 +92,160 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
 #pragma unroll
     for (int j = 0; j < FJ; ++j) acc[i][j] = f4_t{};
 
-  // TBM (TBN) rows x 64 k per operand and slab in 16-byte vectors, VA (VB) per thread
-  u4_t ra[VA], rb[VB];
-  const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZeroBf16);
-  // exact tiling: wave-uniform slab base plus a fixed 32-bit offset per load
-  const int r0 = tid >> 3, c0 = (tid & 7) * 8;  // row r0 + RS i of the slab
-  const uint32_t oa = (uint32_t)(r0 * p.lda + c0), ob = (uint32_t)(r0 * p.ldb + c0);
-  const uint32_t sa32 = (uint32_t)(RS * p.lda), sb32 = (uint32_t)(RS * p.ldb);
-  auto gload = [&](int64_t k0) {
-    if constexpr (EXACT) {
+  const int lr = lane & 15, lk = lane >> 4;
+  if constexpr (DMA) {
+    // LDS: per buffer and operand 256 rows x 64 k in 128-byte rows, no
+    // padding (the load writes 64 lanes x 16 bytes = 1 KB contiguous per
+    // instruction); 16-byte segment s of row r sits at segment s ^ (r & 7),
+    // so the eight lanes of a fragment read (rows r..r+7, one segment) hit
+    // eight distinct bank groups.
+    __shared__ __attribute__((aligned(1024))) uint16_t Ad[2][TBM * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t Bd[2][TBN * BK];
+    // load instruction i of wave w covers slab rows DR i + 8 w .. + 7 (DR =
+    // 8 NW rows per round); lane l fills row DR i + 8 w + l / 8, segment l % 8,
+    // with global segment (l % 8) ^ (l / 8)
+    constexpr int DR = 8 * NW;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int lrow = lane >> 3, gseg = (lane & 7) ^ lrow;
+    const uint32_t oa = (uint32_t)((8 * wv + lrow) * p.lda + 8 * gseg);
+    const uint32_t ob = (uint32_t)((8 * wv + lrow) * p.ldb + 8 * gseg);
+    const uint32_t sar = (uint32_t)(DR * p.lda), sbr = (uint32_t)(DR * p.ldb);
+    auto dma = [&](int buf, int64_t k0) {
       const uint16_t* a0 = A + m0 * p.lda + k0;
       const uint16_t* b0 = Bt + n0 * p.ldb + k0;
 #pragma unroll
-      for (int i = 0; i < VA; ++i)
-        ra[i] = load_global(reinterpret_cast<uintptr_t>(a0 + (oa + i * sa32)));
+      for (int i = 0; i < TBM / DR; ++i)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(a0 + (oa + i * sar)),
+            (__attribute__((address_space(3))) void*)(&Ad[buf][(DR * i + 8 * wv) * BK]),
+            16, 0, 0);
 #pragma unroll
-      for (int i = 0; i < VB; ++i)
-        rb[i] = load_global(reinterpret_cast<uintptr_t>(b0 + (ob + i * sb32)));
-    } else {
-      const int64_t gk = k0 + c0;
+      for (int i = 0; i < TBN / DR; ++i)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(b0 + (ob + i * sbr)),
+            (__attribute__((address_space(3))) void*)(&Bd[buf][(DR * i + 8 * wv) * BK]),
+            16, 0, 0);
+    };
+    // fragment (row R, k segment g) at R * 64 + 8 (g ^ (R & 7)); R & 7 = lr & 7
+    const int arow = (wm * (16 * FI) + lr) * BK, brow = (wn * (16 * FJ) + lr) * BK;
+    const int seg0 = 8 * ((0 * 4 + lk) ^ (lr & 7)), seg1 = 8 * ((1 * 4 + lk) ^ (lr & 7));
+    const int nk = (int)(p.K / BK);
+    dma(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      bf16x8_t af[2][FI], bf[2][FJ];
 #pragma unroll
-      for (int i = 0; i < VA; ++i) {
-        const int64_t ga = m0 + r0 + i * RS;
-        const uintptr_t sa = reinterpret_cast<uintptr_t>(A + ga * p.lda + gk);
-        ra[i] = load_global((ga < p.M && gk < p.K) ? sa : zaddr);
-      }
+      for (int kk = 0; kk < 2; ++kk) {
+        const int sg = kk ? seg1 : seg0;
 #pragma unroll
-      for (int i = 0; i < VB; ++i) {
-        const int64_t gb = n0 + r0 + i * RS;
-        const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
-        rb[i] = load_global((gb < p.N && gk < p.K) ? sb : zaddr);
-      }
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < VA; ++i)
-      *reinterpret_cast<u4_t*>(&As[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = ra[i];
-#pragma unroll
-    for (int i = 0; i < VB; ++i)
-      *reinterpret_cast<u4_t*>(&Bs[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = rb[i];
-  };
-  const int lr = lane & 15, lk = lane >> 4;
-  auto compute = [&](int buf) {
-#pragma unroll
-    for (int kk = 0; kk < BK / 32; ++kk) {
-      bf16x8_t af[FI], bf[FJ];
-#pragma unroll
-      for (int i = 0; i < FI; ++i) {
-        const u4_t x = *reinterpret_cast<const u4_t*>(
-            &As[buf][(wm * (16 * FI) + i * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
-        af[i] = __builtin_bit_cast(bf16x8_t, x);
-      }
-#pragma unroll
-      for (int j = 0; j < FJ; ++j) {
-        const u4_t x = *reinterpret_cast<const u4_t*>(
-            &Bs[buf][(wn * (16 * FJ) + j * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
-        bf[j] = __builtin_bit_cast(bf16x8_t, x);
-      }
-#pragma unroll
-      for (int i = 0; i < FI; ++i)
+        for (int i = 0; i < FI; ++i)
+          af[kk][i] = __builtin_bit_cast(
+              bf16x8_t, *reinterpret_cast<const u4_t*>(&Ad[buf][arow + i * 16 * BK + sg]));
 #pragma unroll
         for (int j = 0; j < FJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+          bf[kk][j] = __builtin_bit_cast(
+              bf16x8_t, *reinterpret_cast<const u4_t*>(&Bd[buf][brow + j * 16 * BK + sg]));
+      }
+      // the other buffer was last read before the previous barrier
+      if (kt + 1 < nk) dma(buf ^ 1, (int64_t)(kt + 1) * BK);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+          for (int j = 0; j < FJ; ++j)
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
+      // keep every MFMA ahead of the wait, so the loads land while they run
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's loads are in LDS
+      __syncthreads();
     }
-  };
+  } else {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TBM * LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TBN * LDS_STRIDE];
+    // TBM (TBN) rows x 64 k per operand and slab in 16-byte vectors, VA (VB) per thread
+    u4_t ra[VA], rb[VB];
+    const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZeroBf16);
+    // exact tiling: wave-uniform slab base plus a fixed 32-bit offset per load
+    const int r0 = tid >> 3, c0 = (tid & 7) * 8;  // row r0 + RS i of the slab
+    const uint32_t oa = (uint32_t)(r0 * p.lda + c0), ob = (uint32_t)(r0 * p.ldb + c0);
+    const uint32_t sa32 = (uint32_t)(RS * p.lda), sb32 = (uint32_t)(RS * p.ldb);
+    auto gload = [&](int64_t k0) {
+      if constexpr (EXACT) {
+        const uint16_t* a0 = A + m0 * p.lda + k0;
+        const uint16_t* b0 = Bt + n0 * p.ldb + k0;
+#pragma unroll
+        for (int i = 0; i < VA; ++i)
+          ra[i] = load_global(reinterpret_cast<uintptr_t>(a0 + (oa + i * sa32)));
+#pragma unroll
+        for (int i = 0; i < VB; ++i)
+          rb[i] = load_global(reinterpret_cast<uintptr_t>(b0 + (ob + i * sb32)));
+      } else {
+        const int64_t gk = k0 + c0;
+#pragma unroll
+        for (int i = 0; i < VA; ++i) {
+          const int64_t ga = m0 + r0 + i * RS;
+          const uintptr_t sa = reinterpret_cast<uintptr_t>(A + ga * p.lda + gk);
+          ra[i] = load_global((ga < p.M && gk < p.K) ? sa : zaddr);
+        }
+#pragma unroll
+        for (int i = 0; i < VB; ++i) {
+          const int64_t gb = n0 + r0 + i * RS;
+          const uintptr_t sb = reinterpret_cast<uintptr_t>(Bt + gb * p.ldb + gk);
+          rb[i] = load_global((gb < p.N && gk < p.K) ? sb : zaddr);
+        }
+      }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < VA; ++i)
+        *reinterpret_cast<u4_t*>(&As[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = ra[i];
+#pragma unroll
+      for (int i = 0; i < VB; ++i)
+        *reinterpret_cast<u4_t*>(&Bs[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = rb[i];
+    };
+    auto compute = [&](int buf) {
+#pragma unroll
+      for (int kk = 0; kk < BK / 32; ++kk) {
+        bf16x8_t af[FI], bf[FJ];
+#pragma unroll
+        for (int i = 0; i < FI; ++i) {
+          const u4_t x = *reinterpret_cast<const u4_t*>(
+              &As[buf][(wm * (16 * FI) + i * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
+          af[i] = __builtin_bit_cast(bf16x8_t, x);
+        }
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) {
+          const u4_t x = *reinterpret_cast<const u4_t*>(
+              &Bs[buf][(wn * (16 * FJ) + j * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
+          bf[j] = __builtin_bit_cast(bf16x8_t, x);
+        }
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+          for (int j = 0; j < FJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+    };
 
-  const int nk = (int)((p.K + BK - 1) / BK);
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk - 1; ++kt) {
-    gload((int64_t)(kt + 1) * BK);
-    // issue the global loads first and keep the LDS stores after all MFMAs
-    __builtin_amdgcn_sched_barrier(0);
-    compute(kt & 1);
-    __builtin_amdgcn_sched_barrier(0);
-    sstore((kt + 1) & 1);
+    const int nk = (int)((p.K + BK - 1) / BK);
+    gload(0);
+    sstore(0);
     __syncthreads();
+    for (int kt = 0; kt < nk - 1; ++kt) {
+      gload((int64_t)(kt + 1) * BK);
+      // issue the global loads first and keep the LDS stores after all MFMAs
+      __builtin_amdgcn_sched_barrier(0);
+      compute(kt & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      sstore((kt + 1) & 1);
+      __syncthreads();
+    }
+    compute((nk - 1) & 1);
   }
-  compute((nk - 1) & 1);
 
   double ss = 0.0;
   const float alpha = (float)p.alpha, diag = (float)p.diag;
@@ -265,13 +343,21 @@ hipError_t launch_gemm_bf16(const GemmPlan& plan, const Bf16GemmArgs& a, hipStre
   if ((a.M + tm - 1) / tm != plan.tiles_m || (a.N + tm - 1) / tm != plan.tiles_n)
     return hipErrorInvalidValue;  // the plan was made for another shape
   const bool exact = a.M % tm == 0 && a.N % tm == 0 && a.K % BK == 0;
+  const char* v = getenv("NN_BF16_DMA");  // 0: stage through registers instead
+  const bool dma = !(v && atoi(v) == 0);
   if (tm == 256) {
-    if (exact)
+    if (exact && dma)
+      hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 2, 4, true, true>), dim3(grid), dim3(512), 0,
+                         s, a, plan.tiles_m, plan.tiles_n);
+    else if (exact)
       hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 2, 4, true>), dim3(grid), dim3(512), 0, s, a,
                          plan.tiles_m, plan.tiles_n);
     else
       hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 2, 4, false>), dim3(grid), dim3(512), 0, s,
                          a, plan.tiles_m, plan.tiles_n);
+  } else if (exact && dma) {
+    hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 2, 2, true, true>), dim3(grid), dim3(256), 0,
+                       s, a, plan.tiles_m, plan.tiles_n);
   } else if (exact) {
     hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 2, 2, true>), dim3(grid), dim3(256), 0, s, a,
                        plan.tiles_m, plan.tiles_n);

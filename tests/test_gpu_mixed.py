@@ -118,26 +118,30 @@ def test_mixed_power_identity_start(n, cond):
 
 @pytest.mark.parametrize("n", [512, 768, 1000])
 def test_bf16_tilings_agree(n, monkeypatch):
-    """The 256 x 256 and 128 x 128 BF16 tilings accumulate every output element
-    over the same k in the same order, so the schedule takes the same steps:
-    equal phase counts, BF16-phase rms equal up to the partials' summation
-    order, and the same final iterate.  n = 1000 exercises the bounds-checked
-    form of both (not a multiple of either tile)."""
+    """The 256 x 256 and 128 x 128 BF16 tilings, each staged through registers
+    or loaded straight into LDS (the latter for exact tilings: n = 512, 768),
+    accumulate every output element over the same k in the same order, so the
+    schedule takes the same steps: equal phase counts, BF16-phase rms equal up
+    to the partials' summation order, and the same final iterate.  n = 1000
+    exercises the bounds-checked form (not a multiple of either tile)."""
     _say(f"bf16 tilings n={n}")
     A = torch.from_numpy(W.dense_spd(n, 1.0, 1e4, 60 + n, log_spectrum=True)).to(DEV)
     res = {}
-    for tile in ("128", "256"):
+    for tile, dma in (("128", "0"), ("128", "1"), ("256", "0"), ("256", "1")):
         monkeypatch.setenv("NN_BF16_TILE", tile)
+        monkeypatch.setenv("NN_BF16_DMA", dma)
         X, info = nn.invert(A, depth=2, x0="identity", tol=1e-12, max_iter=200, prec="mixed")
         torch.cuda.synchronize()
-        assert info["status"] == nn.NN_OK, (tile, info)
-        res[tile] = (X.cpu().numpy(), info)
-    (X1, i1), (X2, i2) = res["128"], res["256"]
-    assert i1["phase_iters"] == i2["phase_iters"]
+        assert info["status"] == nn.NN_OK, (tile, dma, info)
+        res[tile + dma] = (X.cpu().numpy(), info)
+    X1, i1 = res["1280"]
     pb = i1["phase_iters"][0]
     if n % 8 == 0:
         assert pb >= 2
-    for k in range(pb + 1):
-        a, b = i1["trace"][k], i2["trace"][k]
-        assert abs(a - b) <= 1e-12 * b, (k, a, b)
-    assert np.linalg.norm(X1 - X2) <= 1e-13 * np.linalg.norm(X1)
+    for key in ("1281", "2560", "2561"):
+        X2, i2 = res[key]
+        assert i1["phase_iters"] == i2["phase_iters"], key
+        for k in range(pb + 1):
+            a, b = i1["trace"][k], i2["trace"][k]
+            assert abs(a - b) <= 1e-12 * b, (key, k, a, b)
+        assert np.linalg.norm(X1 - X2) <= 1e-13 * np.linalg.norm(X1), key
