@@ -279,7 +279,7 @@ __device__ __host__ __forceinline__ int lds_nbufs(int depth) { return depth >= 3
 // sqrt(K) rms_k < 0.1, the only case in which the next test can fire.  Every
 // decision uses the group-reduced sum, identical in all lanes, so the group's
 // control flow stays uniform.
-template <bool CPLX, int NB, bool SH>
+template <bool CPLX, int NB, bool SH, bool TOL>
 __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, int depth, int x0,
                                            int iters, double tol, int max_iter, int buf,
                                            int bufstride, const Group& g, nn_info_dev* info) {
@@ -365,7 +365,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     }
   }
   g.sync();
-  const bool fixed = iters > 0;
+  constexpr bool fixed = !TOL;  // TOL: iters == 0 (tolerance mode), else iters nests
   const double sqk = sqrt((double)K);
   int k = 0, status = NN_OK;
   double rms = NAN, rms_prev = NAN;
@@ -486,8 +486,10 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
 // Measured on 4096 K = 64 complex matrices: 2.53 ms (four waves per
 // workgroup, ~400 registers), 1.84 ms (four waves, 256 registers, two
 // workgroups per CU), 1.58 ms (eight waves, 128 registers, two per CU; about
-// 1 KB of scratch spills per lane).
-template <bool CPLX>
+// 1 KB of scratch spills per lane).  TOL selects the control mode at compile
+// time (tolerance mode, a.iters == 0, or a fixed number of nests), so the
+// fixed-nest kernel carries none of the per-nest stopping logic.
+template <bool CPLX, bool TOL>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
   __shared__ int item_s;
@@ -516,9 +518,9 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
       nn_info_dev* inf = a.info ? a.info + b : nullptr;
       const int nbw = blocks_per_wave(K, CPLX, kWaves);
       const bool sh = shared_rows(K, CPLX, nbw);
-#define NN_ONE(NB, SH)                                                                        \
-  invert_one<CPLX, NB, SH>(A + off, X + xoff, K, a.depth, a.x0, a.iters, tol, mit, 0, big_stride, \
-                           g, inf)
+#define NN_ONE(NB, SH)                                                                     \
+  invert_one<CPLX, NB, SH, TOL>(A + off, X + xoff, K, a.depth, a.x0, a.iters, tol, mit, 0,   \
+                                big_stride, g, inf)
       switch (nbw * 2 + (sh ? 1 : 0)) {
         case 2:
         case 3: NN_ONE(1, true); break;  // one block per wave always shares its row
@@ -544,8 +546,8 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
         const int nbw = blocks_per_wave(K, CPLX, 1);
         const bool sh = shared_rows(K, CPLX, nbw);
 #define NN_ONE(NB, SH)                                                                     \
-  invert_one<CPLX, NB, SH>(A + off, X + xoff, K, a.depth, a.x0, a.iters, tol, mit, base,   \
-                           wave_stride, g, inf)
+  invert_one<CPLX, NB, SH, TOL>(A + off, X + xoff, K, a.depth, a.x0, a.iters, tol, mit, base, \
+                                wave_stride, g, inf)
         switch (nbw * 2 + (sh ? 1 : 0)) {
           case 2:
           case 3: NN_ONE(1, true); break;  // one block per wave always shares its row
@@ -587,20 +589,30 @@ hipError_t launch_batched(const BatchedArgs& args, hipStream_t s) {
   if (e != hipSuccess) return e;
   const size_t lds = lds_bytes(cplx, a.max_n, a.wave_max_k, a.depth);
   if (cplx) {
-    hipLaunchKernelGGL(batched_nn<true>, dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
+    if (a.iters > 0)
+      hipLaunchKernelGGL((batched_nn<true, false>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
+    else
+      hipLaunchKernelGGL((batched_nn<true, true>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
   } else {
-    hipLaunchKernelGGL(batched_nn<false>, dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
+    if (a.iters > 0)
+      hipLaunchKernelGGL((batched_nn<false, false>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
+    else
+      hipLaunchKernelGGL((batched_nn<false, true>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
   }
   return hipGetLastError();
 }
 
 hipError_t batched_allow_lds() {
   const int lim = 150 * 1024;  // dynamic part; the kernels' static LDS is under 10 KB
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_nn<true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_nn<false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  const void* kernels[4] = {reinterpret_cast<const void*>(&batched_nn<true, false>),
+                            reinterpret_cast<const void*>(&batched_nn<true, true>),
+                            reinterpret_cast<const void*>(&batched_nn<false, false>),
+                            reinterpret_cast<const void*>(&batched_nn<false, true>)};
+  for (const void* k : kernels) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k, int depth) {
