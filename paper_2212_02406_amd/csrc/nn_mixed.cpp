@@ -19,7 +19,10 @@
 //      rms_{k-1} / 2) — the FP32 rounding floor.  A loose tolerance (tol >= 1e-4, far above that floor:
 //      a preconditioner) is met by the FP32 iterate itself: the phase then
 //      runs until the FP32 rms is below tol, and phase D only confirms it.
-//   D  FP64 residual and FP64 refinement nests until rms < tol.
+//   D  FP64 residual and FP64 refinement nests until rms < tol.  A nest
+//      may be deeper or shallower than d when one nest of that depth is
+//      predicted to finish (fp64_nest_depth): from the FP32 floor one depth-3
+//      nest replaces two depth-2 nests.
 //
 // The transpose start squares the condition number (A X_0 = s A A^H); with
 // cond(A) = 1e4 neither the BF16 nor the FP32 phase stays inside the
@@ -93,7 +96,7 @@ MixedWs carve(void* base, int64_t n, int depth) {
   w.X64alt = static_cast<double*>(take(8 * nn));
   w.R64 = static_cast<double*>(take(8 * nn));
   w.U64[0] = static_cast<double*>(take(8 * nn));
-  w.U64[1] = depth >= 3 ? static_cast<double*>(take(8 * nn)) : nullptr;
+  w.U64[1] = static_cast<double*>(take(8 * nn));  // FP64 nests may run deeper than d
   const GemmPlan p64 = plan_gemm(Elem::F64, n, n), p32 = plan_gemm(Elem::F32, n, n),
                  pb = plan_gemm_bf16(n, n);
   const int tiles = std::max({p64.num_tiles(), p32.num_tiles(), pb.num_tiles(), 1});
@@ -119,6 +122,22 @@ int fp64_nests(double r, double p, double tol) {
   return (int)ceil(log(log(tol) / log(r)) / log(p));
 }
 
+// Depth of the next FP64 nest from residual rms r.  A nest of any depth q
+// leaves the residual R^(q+1) (I - A X sum_{i<=q} R^i = R^(q+1)), and from an
+// FP32 iterate the FP64 residual falls at that full order (its error is
+// rounding spread over all modes, not a few slow ones).  So in the asymptotic
+// regime (sqrt(N) r < 0.1) the nest takes the smallest q with r^(q+1) <
+// tol / 10, which finishes in one nest at q + 1 products (Horner, update,
+// final residual), when that is no more than the (d+1)-product nests of
+// depth d predicted at full order; otherwise depth d.  If the prediction
+// falls short, the loop simply runs another nest.
+int fp64_nest_depth(double r, int d, int64_t n, double tol) {
+  if (!(sqrt((double)n) * r < 0.1) || !(r > 0.0) || !(tol > 0.0)) return d;
+  const int q = std::max(1, (int)ceil(log(0.1 * tol) / log(r)) - 1);
+  if (q > NN_MAX_DEPTH) return d;
+  return q + 1 <= fp64_nests(r, d + 1, tol) * (d + 1) ? q : d;
+}
+
 struct Run {
   nn_ctx* ctx;
   int64_t n;
@@ -138,14 +157,14 @@ struct Run {
   }
 };
 
-// One plain nest (FP32 or FP64) after its residual R is known: Horner chain
-// and update X' = X + X U into Xn.
+// One plain nest of depth `depth` (FP32 or FP64) after its residual R is
+// known: Horner chain and update X' = X + X U into Xn.
 template <typename T>
 hipError_t plain_update(Run& r, Elem e, const GemmPlan& plan, const T* X, int64_t ldx, T* Xn,
-                        int64_t ldxn, const T* R, T* const U[2]) {
+                        int64_t ldxn, const T* R, T* const U[2], int depth) {
   const int64_t n = r.n;
   const T* Ucur = R;
-  for (int m = 1; m < r.d; ++m) {
+  for (int m = 1; m < depth; ++m) {
     T* Un = U[(m - 1) & 1];
     GemmArgs g{R, n, Ucur, n, Un, n, R, n, n, n, n, 1.0, 0.0, nullptr};
     hipError_t err = launch_gemm(e, false, plan, g, r.s());
@@ -292,7 +311,8 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
     if (sqrt((double)n) * rms_prev < 0.1 && rms >= 0.5 * rms_prev) break;  // FP32 floor
     rms_prev = rms;
     float* U[2] = {w.U32[0], w.U32[1]};
-    HIP_TRY(plain_update<float>(r, Elem::F32, p32, w.X32[cur], n, w.X32[cur ^ 1], n, w.R32, U));
+    HIP_TRY(plain_update<float>(r, Elem::F32, p32, w.X32[cur], n, w.X32[cur ^ 1], n, w.R32, U,
+                                r.d));
     cur ^= 1;
     ++iters;
     ++phase_it[1];
@@ -328,7 +348,8 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
     if (iters >= max_iter) { st = NN_NOT_CONVERGED; break; }
     rms_prev = rms;
     double* U[2] = {w.U64[0], w.U64[1]};
-    HIP_TRY(plain_update<double>(r, Elem::F64, p64, Xc, ldc, Xo, ldo, w.R64, U));
+    HIP_TRY(plain_update<double>(r, Elem::F64, p64, Xc, ldc, Xo, ldo, w.R64, U,
+                                 fp64_nest_depth(rms, r.d, n, prm->tol)));
     std::swap(Xc, Xo);
     std::swap(ldc, ldo);
     ++iters;
