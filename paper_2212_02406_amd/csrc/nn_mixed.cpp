@@ -14,9 +14,10 @@
 //      Appendix 2; the rms, a mean dominated by the slowest modes, falls with
 //      a smaller effective order p, measured from the last two FP32 nests, and
 //      the FP64 nests needed from rms r are ceil(log_p(log tol / log r))), or
-//      until an FP32 nest no longer takes 5% off the rms or the rms stagnates
-//      in the asymptotic regime (sqrt(N) rms_{k-1} < 0.1 and rms_k >=
-//      rms_{k-1} / 2) — the FP32 rounding floor.  A loose tolerance (tol >= 1e-4, far above that floor:
+//      until an FP32 nest no longer takes 5% off the rms, or lands more than
+//      twice above what the previous nest's order predicts (once the rms is
+//      below 0.05), or the rms stagnates in the asymptotic regime (sqrt(N)
+//      rms_{k-1} < 0.1 and rms_k >= rms_{k-1} / 2) — the FP32 rounding floor.  A loose tolerance (tol >= 1e-4, far above that floor:
 //      a preconditioner) is met by the FP32 iterate itself: the phase then
 //      runs until the FP32 rms is below tol, and phase D only confirms it.
 //   D  FP64 residual and FP64 refinement nests until rms < tol.  A nest
@@ -282,6 +283,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
 
   // ---- phase F: FP32 products until the FP32 rounding floor -------------------
   rms_prev = INFINITY;
+  double p_last = NAN;  // effective order measured on the previous FP32 nest
   for (;;) {
     GemmArgs g{w.A32, n, w.X32[cur], n, w.R32, n, nullptr, 0, n, n, n, -1.0, 1.0, w.part};
     HIP_TRY(launch_gemm(Elem::F32, false, p32, g, s));
@@ -306,7 +308,12 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
       double p = (double)(r.d + 1);
       if (isfinite(rms_prev) && rms_prev < 1.0 && rms < rms_prev && rms > 0.0)
         p = std::min(std::max(log(rms) / log(rms_prev), 1.5), (double)(r.d + 1));
+      // FP32 floor: near convergence (previous rms < 0.05) a nest that lands
+      // more than twice above what the previous nest's order predicts has run
+      // into the rounding of the FP32 residual; the next one would not help.
+      if (isfinite(p_last) && rms_prev < 0.05 && rms > 2.0 * pow(rms_prev, p_last)) break;
       if (fp64_nests(pow(rms, p), p, prm->tol) >= fp64_nests(rms, p, prm->tol)) break;
+      p_last = p;
     }
     if (sqrt((double)n) * rms_prev < 0.1 && rms >= 0.5 * rms_prev) break;  // FP32 floor
     rms_prev = rms;
