@@ -326,14 +326,14 @@ __global__ void __launch_bounds__(256) sparse_step(const int32_t* rp, const int3
 #pragma unroll
       for (int u = 0; u < U; ++u) sr[u] = si[u] = T(0);
       for (int k = 0; k < maxlen; ++k) {
-        // a row shorter than k re-reads its own last entry (any entry for an
-        // empty row: maxlen > 0 implies nnz > 0) with weight 0
+        // a row shorter than k re-reads its own last entry, an empty row entry
+        // 0 (maxlen > 0 implies nnz > 0) with weight 0
         int32_t col[U];
         T ar[U], ai[U], m[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int32_t kk = k < len[u] ? k : (len[u] > 0 ? len[u] - 1 : 0);
-          const int32_t j = j0[u] + kk;
+          // an empty row reads entry 0 (its row_ptr may equal nnz)
+          const int32_t j = len[u] > 0 ? j0[u] + (k < len[u] ? k : len[u] - 1) : 0;
           m[u] = k < len[u] ? T(1) : T(0);
           col[u] = ci[j];
           ar[u] = val[(int64_t)j * C];
@@ -366,6 +366,91 @@ __global__ void __launch_bounds__(256) sparse_step(const int32_t* rp, const int3
           const double m2 = (double)rr * (double)rr + (double)ri * (double)ri;
           accw += wr * m2;
           accp += m2;
+        }
+      }
+    }
+  }
+  block_sum2(accw, accp, sa, sb);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = accw;
+    part[2 * blockIdx.x + 1] = accp;
+  }
+}
+
+// The same term with two adjacent right-hand-side columns per lane (real
+// types; even nrhs and leading dimensions, rows aligned to two elements):
+// every x gather, B read and x store is one two-element vector access, so a
+// wave moves twice the bytes per load instruction.  Loads stay unconditional
+// as above.
+template <typename T, int G>
+__global__ void __launch_bounds__(256) sparse_step2(const int32_t* rp, const int32_t* ci,
+                                                    const T* val, int64_t n, int64_t nrhs,
+                                                    const T* B, int64_t ldb, const T* xin,
+                                                    int64_t ldxi, T* xout, int64_t ldxo,
+                                                    const double* theta, const T* dinv,
+                                                    const double* wdiag, double* part,
+                                                    const SparseCtl* ctl, int update) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  if (ctl->done) return;
+  __shared__ double sa[256], sb[256];
+  constexpr int RPB = 256 / G;
+  constexpr int U = rows_in_flight(G);
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  const int32_t nlast = (int32_t)(n - 1);
+  double accw = 0.0, accp = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * RPB * U; base < n;
+       base += (int64_t)gridDim.x * RPB * U) {
+    int32_t j0[U], len[U];
+    int maxlen = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = base + u * RPB + grp;
+      const int32_t rc = r < n ? (int32_t)r : nlast;
+      const int32_t a = rp[rc], b = rp[rc + 1];
+      j0[u] = a;
+      len[u] = r < n ? b - a : 0;
+      maxlen = len[u] > maxlen ? len[u] : maxlen;
+    }
+    for (int64_t c = 2 * lane; c < nrhs; c += 2 * G) {
+      T2 sr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sr[u] = T2{T(0), T(0)};
+      for (int k = 0; k < maxlen; ++k) {
+        int32_t col[U];
+        T a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          // an empty row reads entry 0 (its row_ptr may equal nnz)
+          const int32_t j = len[u] > 0 ? j0[u] + (k < len[u] ? k : len[u] - 1) : 0;
+          col[u] = ci[j];
+          a[u] = (k < len[u] ? T(1) : T(0)) * val[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const T2 x = *reinterpret_cast<const T2*>(&xin[(int64_t)col[u] * ldxi + c]);
+          sr[u] += a[u] * x;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = base + u * RPB + grp;
+        const int64_t rc = r < n ? r : n - 1;
+        const T2 rr = *reinterpret_cast<const T2*>(&B[rc * ldb + c]) - sr[u];
+        const double wr = wdiag ? wdiag[rc] : 1.0;
+        if (r < n) {
+          if (update) {
+            T p0, p1, unused;
+            phi_mul<T, false>(theta, dinv, r, rr.x, T(0), p0, unused);
+            phi_mul<T, false>(theta, dinv, r, rr.y, T(0), p1, unused);
+            const T2 xv = *reinterpret_cast<const T2*>(&xin[r * ldxi + c]);
+            *reinterpret_cast<T2*>(&xout[r * ldxo + c]) = xv + T2{p0, p1};
+          }
+          const double m0 = (double)rr.x * (double)rr.x, m1 = (double)rr.y * (double)rr.y;
+          accw += wr * m0;
+          accw += wr * m1;
+          accp += m0;
+          accp += m1;
         }
       }
     }
@@ -539,6 +624,18 @@ struct Launch {
                        static_cast<const T*>(dinv), wdiag, part, ctl, update);
     return hipGetLastError();
   }
+  template <int G>
+  static hipError_t step2_g(const int32_t* rp, const int32_t* ci, const void* v, int64_t n,
+                            int64_t nrhs, const void* B, int64_t ldb, const void* xin,
+                            int64_t ldxi, void* xout, int64_t ldxo, const double* theta,
+                            const void* dinv, const double* wdiag, double* part,
+                            const SparseCtl* ctl, int update, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((sparse_step2<T, G>), dim3(nb), dim3(256), 0, s, rp, ci,
+                       static_cast<const T*>(v), n, nrhs, static_cast<const T*>(B), ldb,
+                       static_cast<const T*>(xin), ldxi, static_cast<T*>(xout), ldxo, theta,
+                       static_cast<const T*>(dinv), wdiag, part, ctl, update);
+    return hipGetLastError();
+  }
 };
 
 #define NN_SP_G(G_, CALL) \
@@ -563,14 +660,29 @@ hipError_t launch_init(int g, int64_t n, int64_t nrhs, const void* B, int64_t ld
 }
 
 template <typename T, bool CPLX>
-hipError_t launch_step(int g, const int32_t* rp, const int32_t* ci, const void* v, int64_t n,
-                       int64_t nrhs, const void* B, int64_t ldb, const void* xin, int64_t ldxi,
-                       void* xout, int64_t ldxo, const double* theta, const void* dinv,
-                       const double* wdiag, double* part, const SparseCtl* ctl, int update,
-                       int nb, hipStream_t s) {
+hipError_t launch_step(bool vec2, int g, const int32_t* rp, const int32_t* ci, const void* v,
+                       int64_t n, int64_t nrhs, const void* B, int64_t ldb, const void* xin,
+                       int64_t ldxi, void* xout, int64_t ldxo, const double* theta,
+                       const void* dinv, const double* wdiag, double* part,
+                       const SparseCtl* ctl, int update, int nb, hipStream_t s) {
   using L = Launch<T, CPLX>;
 #define NN_SP_STEP_ARGS \
   rp, ci, v, n, nrhs, B, ldb, xin, ldxi, xout, ldxo, theta, dinv, wdiag, part, ctl, update, nb, s
+  if constexpr (!CPLX) {
+    if (vec2) {
+      switch (g) {
+        NN_SP_G(1, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_G(2, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_G(4, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_G(8, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_G(16, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_G(32, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_G(64, L::template step2_g)(NN_SP_STEP_ARGS);
+      }
+      return hipErrorInvalidValue;
+    }
+  }
+  if (vec2) return hipErrorInvalidValue;
   switch (g) {
     NN_SP_G(1, L::template step_g)(NN_SP_STEP_ARGS);
     NN_SP_G(2, L::template step_g)(NN_SP_STEP_ARGS);
@@ -677,7 +789,13 @@ nn_status nn_solve_sparse(nn_ctx* ctx, const int32_t* row_ptr, const int32_t* co
   const SparseWs w = carve(ws, n, nrhs, dt);
   hipStream_t s = ctx->stream;
   const Ops ops{dt};
-  const int g = lanes_for(nrhs);
+  // two columns per lane for real types when every row of B and of the three
+  // iterate buffers starts on a two-element boundary
+  const size_t esz = (dt == NN_F64) ? 8 : 4;
+  const bool vec2 = (dt == NN_F64 || dt == NN_F32) && nrhs % 2 == 0 && ldb % 2 == 0 &&
+                    ldx % 2 == 0 && reinterpret_cast<uintptr_t>(B) % (2 * esz) == 0 &&
+                    reinterpret_cast<uintptr_t>(Xsol) % (2 * esz) == 0;
+  const int g = lanes_for(vec2 ? nrhs / 2 : nrhs);
   const int64_t rpb = 256 / g * rows_in_flight(g);  // rows per block and step iteration
   const int nb = (int)std::min<int64_t>((n + rpb - 1) / rpb, kSpBlocks);
 
@@ -746,8 +864,8 @@ nn_status nn_solve_sparse(nn_ctx* ctx, const int32_t* row_ptr, const int32_t* co
     int enq = 0;
     for (; t <= last && enq < every; ++t, ++enq) {
       const int i = (int)(t % 3), o = (int)((t + 1) % 3);
-      HIP_TRY(ops.step(g, row_ptr, col_idx, values, n, nrhs, B, ldb, buf[i], ld[i], buf[o], ld[o],
-                       theta, dinv, wdiag, w.part, w.ctl, t < last ? 1 : 0, nb, s));
+      HIP_TRY(ops.step(vec2, g, row_ptr, col_idx, values, n, nrhs, B, ldb, buf[i], ld[i], buf[o],
+                       ld[o], theta, dinv, wdiag, w.part, w.ctl, t < last ? 1 : 0, nb, s));
       hipLaunchKernelGGL(sparse_check, dim3(1), dim3(256), 0, s, w.ctl, w.part, nb, (int32_t)t);
       HIP_TRY(hipGetLastError());
     }

@@ -145,3 +145,23 @@ def test_bf16_tilings_agree(n, monkeypatch):
             a, b = i1["trace"][k], i2["trace"][k]
             assert abs(a - b) <= 1e-12 * b, (key, k, a, b)
         assert np.linalg.norm(X1 - X2) <= 1e-13 * np.linalg.norm(X1), key
+
+
+@pytest.mark.parametrize("n", [1024, 1536])
+def test_single_fp64_nest_from_the_fp32_floor(n):
+    """From the FP32 floor the FP64 residual falls at full order, so one FP64
+    nest, of the smallest depth predicted to finish, takes it below tol: one
+    FP64 nest, rms < tol, and the iterate agrees with LAPACK's inverse within
+    the residual bound."""
+    _say(f"mixed one FP64 nest n={n}")
+    A = W.dense_spd(n, 1.0, 1e4, 80 + n, log_spectrum=True)
+    X, info = nn.invert(torch.from_numpy(A).to(DEV), depth=2, x0="identity", tol=1e-11,
+                        max_iter=200, prec="mixed")
+    torch.cuda.synchronize()
+    assert info["status"] == nn.NN_OK and info["rms"] < 1e-11, info
+    pb, pf, pd = info["phase_iters"]
+    assert pd == 1, info["phase_iters"]
+    Xi = np.linalg.inv(A)
+    rel = np.linalg.norm(X.cpu().numpy() - Xi) / np.linalg.norm(Xi)
+    # X - A^-1 = -A^-1 R: relative error <= sqrt(n) rms, plus LAPACK's own cond * u
+    assert rel < 2.0 * np.sqrt(n) * info["rms"] + 1e-11, rel
