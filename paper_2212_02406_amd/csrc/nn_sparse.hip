@@ -19,6 +19,7 @@
 // control block every check_every terms.  The CSR structure is checked on the
 // device before the first product.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -377,12 +378,13 @@ __global__ void __launch_bounds__(256) sparse_step(const int32_t* rp, const int3
   }
 }
 
-// The same term with two adjacent right-hand-side columns per lane (real
-// types; even nrhs and leading dimensions, rows aligned to two elements):
-// every x gather, B read and x store is one two-element vector access, so a
-// wave moves twice the bytes per load instruction.  Loads stay unconditional
+// The same term with V = 2 or 4 adjacent right-hand-side columns per lane
+// (real types; nrhs and leading dimensions multiples of V, rows aligned to V
+// elements): every x gather, B read and x store is one V-element vector
+// access, so a wave moves V times the bytes per load instruction and the
+// index and value loads are shared by V columns.  Loads stay unconditional
 // as above.
-template <typename T, int G>
+template <typename T, int G, int V>
 __global__ void __launch_bounds__(256) sparse_step2(const int32_t* rp, const int32_t* ci,
                                                     const T* val, int64_t n, int64_t nrhs,
                                                     const T* B, int64_t ldb, const T* xin,
@@ -390,7 +392,7 @@ __global__ void __launch_bounds__(256) sparse_step2(const int32_t* rp, const int
                                                     const double* theta, const T* dinv,
                                                     const double* wdiag, double* part,
                                                     const SparseCtl* ctl, int update) {
-  typedef T T2 __attribute__((ext_vector_type(2)));
+  typedef T T2 __attribute__((ext_vector_type(V)));
   if (ctl->done) return;
   __shared__ double sa[256], sb[256];
   constexpr int RPB = 256 / G;
@@ -412,10 +414,10 @@ __global__ void __launch_bounds__(256) sparse_step2(const int32_t* rp, const int
       len[u] = r < n ? b - a : 0;
       maxlen = len[u] > maxlen ? len[u] : maxlen;
     }
-    for (int64_t c = 2 * lane; c < nrhs; c += 2 * G) {
+    for (int64_t c = V * lane; c < nrhs; c += V * G) {
       T2 sr[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) sr[u] = T2{T(0), T(0)};
+      for (int u = 0; u < U; ++u) sr[u] = T2(T(0));
       for (int k = 0; k < maxlen; ++k) {
         int32_t col[U];
         T a[U];
@@ -440,17 +442,22 @@ __global__ void __launch_bounds__(256) sparse_step2(const int32_t* rp, const int
         const double wr = wdiag ? wdiag[rc] : 1.0;
         if (r < n) {
           if (update) {
-            T p0, p1, unused;
-            phi_mul<T, false>(theta, dinv, r, rr.x, T(0), p0, unused);
-            phi_mul<T, false>(theta, dinv, r, rr.y, T(0), p1, unused);
+            T2 pv;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              T pq, unused;
+              phi_mul<T, false>(theta, dinv, r, rr[q], T(0), pq, unused);
+              pv[q] = pq;
+            }
             const T2 xv = *reinterpret_cast<const T2*>(&xin[r * ldxi + c]);
-            *reinterpret_cast<T2*>(&xout[r * ldxo + c]) = xv + T2{p0, p1};
+            *reinterpret_cast<T2*>(&xout[r * ldxo + c]) = xv + pv;
           }
-          const double m0 = (double)rr.x * (double)rr.x, m1 = (double)rr.y * (double)rr.y;
-          accw += wr * m0;
-          accw += wr * m1;
-          accp += m0;
-          accp += m1;
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            const double mq = (double)rr[q] * (double)rr[q];
+            accw += wr * mq;
+            accp += mq;
+          }
         }
       }
     }
@@ -624,13 +631,13 @@ struct Launch {
                        static_cast<const T*>(dinv), wdiag, part, ctl, update);
     return hipGetLastError();
   }
-  template <int G>
+  template <int G, int V>
   static hipError_t step2_g(const int32_t* rp, const int32_t* ci, const void* v, int64_t n,
                             int64_t nrhs, const void* B, int64_t ldb, const void* xin,
                             int64_t ldxi, void* xout, int64_t ldxo, const double* theta,
                             const void* dinv, const double* wdiag, double* part,
                             const SparseCtl* ctl, int update, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((sparse_step2<T, G>), dim3(nb), dim3(256), 0, s, rp, ci,
+    hipLaunchKernelGGL((sparse_step2<T, G, V>), dim3(nb), dim3(256), 0, s, rp, ci,
                        static_cast<const T*>(v), n, nrhs, static_cast<const T*>(B), ldb,
                        static_cast<const T*>(xin), ldxi, static_cast<T*>(xout), ldxo, theta,
                        static_cast<const T*>(dinv), wdiag, part, ctl, update);
@@ -660,7 +667,7 @@ hipError_t launch_init(int g, int64_t n, int64_t nrhs, const void* B, int64_t ld
 }
 
 template <typename T, bool CPLX>
-hipError_t launch_step(bool vec2, int g, const int32_t* rp, const int32_t* ci, const void* v,
+hipError_t launch_step(int vec, int g, const int32_t* rp, const int32_t* ci, const void* v,
                        int64_t n, int64_t nrhs, const void* B, int64_t ldb, const void* xin,
                        int64_t ldxi, void* xout, int64_t ldxo, const double* theta,
                        const void* dinv, const double* wdiag, double* part,
@@ -668,21 +675,27 @@ hipError_t launch_step(bool vec2, int g, const int32_t* rp, const int32_t* ci, c
   using L = Launch<T, CPLX>;
 #define NN_SP_STEP_ARGS \
   rp, ci, v, n, nrhs, B, ldb, xin, ldxi, xout, ldxo, theta, dinv, wdiag, part, ctl, update, nb, s
+#define NN_SP_GV(G_, V_) \
+  case G_:               \
+    return L::template step2_g<G_, V_>(NN_SP_STEP_ARGS)
   if constexpr (!CPLX) {
-    if (vec2) {
+    if (vec == 2) {
       switch (g) {
-        NN_SP_G(1, L::template step2_g)(NN_SP_STEP_ARGS);
-        NN_SP_G(2, L::template step2_g)(NN_SP_STEP_ARGS);
-        NN_SP_G(4, L::template step2_g)(NN_SP_STEP_ARGS);
-        NN_SP_G(8, L::template step2_g)(NN_SP_STEP_ARGS);
-        NN_SP_G(16, L::template step2_g)(NN_SP_STEP_ARGS);
-        NN_SP_G(32, L::template step2_g)(NN_SP_STEP_ARGS);
-        NN_SP_G(64, L::template step2_g)(NN_SP_STEP_ARGS);
+        NN_SP_GV(1, 2); NN_SP_GV(2, 2); NN_SP_GV(4, 2); NN_SP_GV(8, 2);
+        NN_SP_GV(16, 2); NN_SP_GV(32, 2); NN_SP_GV(64, 2);
+      }
+      return hipErrorInvalidValue;
+    }
+    if (vec == 4) {
+      switch (g) {
+        NN_SP_GV(1, 4); NN_SP_GV(2, 4); NN_SP_GV(4, 4); NN_SP_GV(8, 4);
+        NN_SP_GV(16, 4); NN_SP_GV(32, 4); NN_SP_GV(64, 4);
       }
       return hipErrorInvalidValue;
     }
   }
-  if (vec2) return hipErrorInvalidValue;
+#undef NN_SP_GV
+  if (vec != 1) return hipErrorInvalidValue;
   switch (g) {
     NN_SP_G(1, L::template step_g)(NN_SP_STEP_ARGS);
     NN_SP_G(2, L::template step_g)(NN_SP_STEP_ARGS);
@@ -789,13 +802,20 @@ nn_status nn_solve_sparse(nn_ctx* ctx, const int32_t* row_ptr, const int32_t* co
   const SparseWs w = carve(ws, n, nrhs, dt);
   hipStream_t s = ctx->stream;
   const Ops ops{dt};
-  // two columns per lane for real types when every row of B and of the three
-  // iterate buffers starts on a two-element boundary
+  // V = 2 columns per lane for real types when every row of B and of the
+  // three iterate buffers starts on a two-element boundary, else 1.  V = 4
+  // (NN_SPARSE_VEC=4) measured slower on the 2048^2 Laplacian with 16
+  // right-hand sides: 0.564 against 0.522 ms per term.
   const size_t esz = (dt == NN_F64) ? 8 : 4;
-  const bool vec2 = (dt == NN_F64 || dt == NN_F32) && nrhs % 2 == 0 && ldb % 2 == 0 &&
-                    ldx % 2 == 0 && reinterpret_cast<uintptr_t>(B) % (2 * esz) == 0 &&
-                    reinterpret_cast<uintptr_t>(Xsol) % (2 * esz) == 0;
-  const int g = lanes_for(vec2 ? nrhs / 2 : nrhs);
+  auto fits = [&](int v) {
+    return (dt == NN_F64 || dt == NN_F32) && nrhs % v == 0 && ldb % v == 0 && ldx % v == 0 &&
+           reinterpret_cast<uintptr_t>(B) % (v * esz) == 0 &&
+           reinterpret_cast<uintptr_t>(Xsol) % (v * esz) == 0;
+  };
+  const char* vv = getenv("NN_SPARSE_VEC");  // 1, 2 or 4: the largest width tried
+  const int vmax = vv ? atoi(vv) : 2;
+  const int vec = (vmax >= 4 && fits(4)) ? 4 : (vmax >= 2 && fits(2)) ? 2 : 1;
+  const int g = lanes_for(nrhs / vec);
   const int64_t rpb = 256 / g * rows_in_flight(g);  // rows per block and step iteration
   const int nb = (int)std::min<int64_t>((n + rpb - 1) / rpb, kSpBlocks);
 
@@ -864,7 +884,7 @@ nn_status nn_solve_sparse(nn_ctx* ctx, const int32_t* row_ptr, const int32_t* co
     int enq = 0;
     for (; t <= last && enq < every; ++t, ++enq) {
       const int i = (int)(t % 3), o = (int)((t + 1) % 3);
-      HIP_TRY(ops.step(vec2, g, row_ptr, col_idx, values, n, nrhs, B, ldb, buf[i], ld[i], buf[o],
+      HIP_TRY(ops.step(vec, g, row_ptr, col_idx, values, n, nrhs, B, ldb, buf[i], ld[i], buf[o],
                        ld[o], theta, dinv, wdiag, w.part, w.ctl, t < last ? 1 : 0, nb, s));
       hipLaunchKernelGGL(sparse_check, dim3(1), dim3(256), 0, s, w.ctl, w.part, nb, (int32_t)t);
       HIP_TRY(hipGetLastError());
