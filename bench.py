@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=192)
     ap.add_argument("--host-input", action="store_true",
-                    help="build the headline matrix with host (NumPy) QR only, no GPU library "
+                    help="build the headline and mixed-leg matrices with host (NumPy) QR only, no GPU library "
                          "kernels before the NN launches (for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 1 GiB device copies (untimed), the reference "
@@ -215,11 +215,12 @@ def leg_batched(nn, torch, workloads, np):
     return out
 
 
-def leg_mixed(nn, torch, workloads, np, n):
+def leg_mixed(nn, torch, workloads, np, n, host_input=False):
     """Dense SPD N=16384, cond 1e4 (log-uniform spectrum), depth 2, tol 1e-11:
     mixed BF16/FP32/FP64 schedule vs plain FP64, each from the scaled
     identity start I / Tr A and from Theta_2(8) I."""
-    A_h, lam, Q = workloads.dense_spd(n, 1.0, 1e4, 4, log_spectrum=True, device="cuda",
+    A_h, lam, Q = workloads.dense_spd(n, 1.0, 1e4, 4, log_spectrum=True,
+                                      device=None if host_input else "cuda",
                                       return_factors=True)
     A = torch.from_numpy(A_h).cuda()
     torch.cuda.synchronize()
@@ -608,7 +609,7 @@ def main():
     if "batched" in legs:
         extra["batched"] = leg_batched(nn, torch, workloads, np)
     if "mixed" in legs:
-        extra["mixed"] = leg_mixed(nn, torch, workloads, np, args.mixed_n)
+        extra["mixed"] = leg_mixed(nn, torch, workloads, np, args.mixed_n, args.host_input)
         torch.cuda.empty_cache()
     if "serving" in legs:
         extra["serving"] = leg_serving(nn, torch, workloads, np, args.serve_pool,
