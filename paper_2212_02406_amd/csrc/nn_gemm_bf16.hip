@@ -16,10 +16,13 @@
 // of 64 x 64 (any shape), and 256 x 256 x 64 with 8 waves of 128 x 64 for large
 // products (a wave reads 8 + 4 fragments for 32 MFMAs instead of 4 + 4 for 16).
 // Both use two LDS buffers and the XCD-aware tile order of the FP64/FP32
-// kernel.  For exact tilings the operands are loaded straight into
-// LDS (global_load_lds_dwordx4: lane l of a wave writes bytes 16 l .. 16 l + 15
-// of a 1 KB block, measured on gfx950) into XOR-swizzled rows, which frees
-// the staging registers and the LDS store instructions.  Every output element
+// kernel.  LDS rows are 128 bytes (64 k) with the 16-byte segment s of row r
+// stored at s ^ (r & 7), so the eight rows of a fragment read hit distinct
+// banks (padded rows conflicted on gfx950).  For exact tilings the operands
+// are loaded straight into LDS (global_load_lds_dwordx4: lane l of a wave
+// writes bytes 16 l .. 16 l + 15 of a 1 KB block, measured on gfx950), which
+// frees the staging registers and the LDS store instructions; other shapes
+// stage through registers into the same layout.  Every output element
 // is accumulated over the same k in the same order by the same instruction in
 // all forms, so C is the same bits; only the per-tile partials differ.
 #include <stdlib.h>
@@ -34,7 +37,6 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 64;
-constexpr int LDS_STRIDE = BK + 8;  // bf16 elements; 144-byte rows: conflict-free 16-byte reads
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
@@ -164,8 +166,9 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
       __syncthreads();
     }
   } else {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][TBM * LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TBN * LDS_STRIDE];
+    // the same swizzled 128-byte rows as above (padded rows conflict on gfx950)
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TBM * BK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TBN * BK];
     // TBM (TBN) rows x 64 k per operand and slab in 16-byte vectors, VA (VB) per thread
     u4_t ra[VA], rb[VB];
     const uintptr_t zaddr = reinterpret_cast<uintptr_t>(kZeroBf16);
@@ -199,28 +202,32 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
         }
       }
     };
+    // row R's global segment c0 / 8 goes to segment (c0 / 8) ^ (R & 7); R & 7 =
+    // r0 & 7 for every i (RS is a multiple of 8)
+    const int sseg = 8 * ((c0 >> 3) ^ (r0 & 7));
     auto sstore = [&](int buf) {
 #pragma unroll
       for (int i = 0; i < VA; ++i)
-        *reinterpret_cast<u4_t*>(&As[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = ra[i];
+        *reinterpret_cast<u4_t*>(&As[buf][(r0 + i * RS) * BK + sseg]) = ra[i];
 #pragma unroll
       for (int i = 0; i < VB; ++i)
-        *reinterpret_cast<u4_t*>(&Bs[buf][(r0 + i * RS) * LDS_STRIDE + c0]) = rb[i];
+        *reinterpret_cast<u4_t*>(&Bs[buf][(r0 + i * RS) * BK + sseg]) = rb[i];
     };
     auto compute = [&](int buf) {
 #pragma unroll
       for (int kk = 0; kk < BK / 32; ++kk) {
         bf16x8_t af[FI], bf[FJ];
+        const int sg = 8 * ((kk * 4 + lk) ^ (lr & 7));  // rows of a fragment: R & 7 = lr & 7
 #pragma unroll
         for (int i = 0; i < FI; ++i) {
           const u4_t x = *reinterpret_cast<const u4_t*>(
-              &As[buf][(wm * (16 * FI) + i * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
+              &As[buf][(wm * (16 * FI) + i * 16 + lr) * BK + sg]);
           af[i] = __builtin_bit_cast(bf16x8_t, x);
         }
 #pragma unroll
         for (int j = 0; j < FJ; ++j) {
           const u4_t x = *reinterpret_cast<const u4_t*>(
-              &Bs[buf][(wn * (16 * FJ) + j * 16 + lr) * LDS_STRIDE + kk * 32 + 8 * lk]);
+              &Bs[buf][(wn * (16 * FJ) + j * 16 + lr) * BK + sg]);
           bf[j] = __builtin_bit_cast(bf16x8_t, x);
         }
 #pragma unroll
