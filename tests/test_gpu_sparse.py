@@ -200,3 +200,32 @@ def test_full_size_laplacian_2048sq_closed_form():
     assert info["status"] == nn.NN_OK and info["rms"] < 1e-10
     kappa = (8 + shift) / shift
     assert _relF(X.cpu().numpy(), B / lam[None, :]) <= kappa * info["rel_residual"] * 1.01
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nrhs,ldb", [(16, 16), (12, 12), (8, 10), (6, 6)])
+def test_vector_widths_agree(dtype, nrhs, ldb, monkeypatch):
+    """Real types take 2 (default) or 4 adjacent right-hand-side columns per
+    lane when nrhs, the leading dimensions and the row alignment allow, else
+    one.  Every width computes the same series: each against the oracle at
+    fixed terms, and the widths against each other (they differ only in the
+    grouping of the control sums)."""
+    _say(f"sparse widths nrhs={nrhs} ldb={ldb} {np.dtype(dtype).name}")
+    ip, ix, v, B = _case(700, nrhs, 990 + nrhs, dtype)
+    xo, _ = nn_sparse_solve_ref(ip, ix, v.astype(np.float64), B.astype(np.float64),
+                                x0=X0["jacobi"], fixed_terms=12)
+    if dtype == np.float64:
+        bound = same = 1e-10
+    else:  # FP32 rounding of the inputs and of 12 terms, amplified by the conditioning
+        kappa = np.linalg.cond(W.csr_to_dense(ip, ix, v.astype(np.float64), 700))
+        bound = same = 64 * U32 * kappa
+    res = {}
+    for vmax in ("1", "2", "4"):
+        monkeypatch.setenv("NN_SPARSE_VEC", vmax)
+        X, info = _solve(ip, ix, v, B, ldb, x0="jacobi", fixed_terms=12)
+        torch.cuda.synchronize()
+        assert info["status"] == nn.NN_OK and info["iters"] == 12, (vmax, info["status"])
+        res[vmax] = X.cpu().numpy()
+        assert _relF(res[vmax], xo) < bound, vmax
+    for vmax in ("2", "4"):
+        assert _relF(res[vmax], res["1"]) < same, vmax
