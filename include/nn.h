@@ -11,8 +11,8 @@
  *     U_1 = R,  U_{m+1} = R + R U_m     (d - 1 GEMMs, Horner form)
  *     X'  = X + X U_d                   (update)
  * which equals X (I + R + ... + R^d) (Sec. II-D cost model: L + 1 products
- * per nest).  rms = ||I - A X||_F / sqrt(N) (Sec. II, "root mean Frobenius
- * norm error").
+ * per nest).  rms = ||I - A X||_F / sqrt(N), the paper's root-mean
+ * Frobenius accuracy measure (Sec. II).
  *
  * Conventions for every entry point:
  *  - Matrices are dense, row-major, with a leading dimension (in elements)
@@ -130,6 +130,9 @@ typedef struct {
   int32_t gemms;      /* GEMM launches made (k (d+1) + 1 for k nests) */
   int32_t n_trace;    /* entries used in rms_trace */
   int32_t phase_iters[3]; /* mixed: nests in the BF16, FP32, FP64 phases */
+  int32_t prec_gemms[3];  /* GEMM launches by arithmetic: BF16 inputs with FP32
+                             accumulation, FP32 (and complex64), FP64 (and
+                             complex128); they sum to gemms */
   double rms_trace[NN_TRACE_MAX]; /* rms_0, rms_1, ... as computed */
 } nn_info;
 
@@ -361,22 +364,39 @@ nn_status nn_invert_batched(nn_ctx* ctx, const void* A_packed, void* X_packed,
 
 /* Autotune nn_invert_batched for this batch: time each candidate kernel
  * configuration (size up to which a matrix gets one wave instead of a whole
- * workgroup: 0, 8, 16, 32; workgroups per CU: 1, 2, 4, ... as LDS allows) on
- * the given arguments, three replays each, and keep the fastest in the
- * context for later calls with the same dtype and max_n.  Arguments as for
- * nn_invert_batched; X_packed is overwritten.  *best_ms (optional) receives
- * the best replay time.  Blocks until done. */
+ * workgroup: 0, 8, 16, 32, those whose LDS fits at params->depth; workgroups
+ * per CU: 1, 2, 4, ... as LDS allows; candidates that give the same launch
+ * are timed once) on the given arguments, three replays each, and keep the
+ * fastest in the context for later calls with the same dtype and max_n.
+ * Arguments as for nn_invert_batched; X_packed is overwritten.  *best_ms
+ * (optional) receives the best replay time.  Blocks until done.
+ *   Persistence: if the environment variable NN_AUTOTUNE_CACHE names a file,
+ *   an entry for (device architecture, dtype, max_n) found there is taken
+ *   instead of timing anything (*from_cache = 1, *best_ms = the stored time,
+ *   X_packed untouched); otherwise the tuned result is appended to the file
+ *   (*from_cache = 0).  Lines: "<arch> <dtype> <max_n> <wave_max_k>
+ *   <wg_per_cu> <ms>"; the last matching line wins.  from_cache may be NULL. */
 nn_status nn_batched_autotune(nn_ctx* ctx, const void* A_packed, void* X_packed,
                               const int64_t* offsets, const int32_t* sizes, int32_t batch,
                               int32_t max_n, nn_dtype dtype, const nn_params* params,
-                              void* ws, size_t ws_bytes, float* best_ms);
+                              void* ws, size_t ws_bytes, float* best_ms, int32_t* from_cache);
 
 /* Read / set the batched kernel configuration the context uses for (dtype,
- * max_n): wave_max_k in [0, 32], wg_per_cu in [1, 8]. */
+ * max_n): wave_max_k in [0, 32], wg_per_cu in [1, 8].  At launch, wave_max_k
+ * is lowered (32 -> 16 -> 8 -> 0) until the LDS of one workgroup holds the
+ * call's depth (nn_batched_fit_config), and the environment variable
+ * NN_BATCHED_GRID (a positive integer), if set, replaces the number of
+ * persistent workgroups (results do not depend on it). */
 nn_status nn_batched_get_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
                                 int32_t* wave_max_k, int32_t* wg_per_cu);
 nn_status nn_batched_set_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n,
                                 int32_t wave_max_k, int32_t wg_per_cu);
+
+/* The one-wave size limit a batched launch uses for a configured wave_max_k
+ * at depth `depth`: the largest of wave_max_k, 16, 8, 0 (not above it, nor
+ * above max_n) whose LDS fits one workgroup (150 KB of dynamic LDS and
+ * 160 KB in all on one CU).  -1 on bad arguments.  Needs no device. */
+int32_t nn_batched_fit_config(nn_dtype dtype, int32_t max_n, int32_t wave_max_k, int32_t depth);
 
 /* ---------------------------------------------------------------------------
  * Continuous-batching server.

@@ -5,8 +5,8 @@ HIP library computes, written from the paper (Engsig, Yang, Mehouachi,
 "Generalization of higher order methods for fast iterative matrix inversion
 via GPU acceleration", arXiv 2212.02406):
 
-* ``nn_fp64``  — ``nn_ref``, the NN iteration in FP64 / complex128 NumPy, step by step, in
-                 the order of Algorithm 1 (Section III), with the stopping and
+* ``nn_fp64``  — ``nn_ref``, the NN iteration in FP64 / complex128 NumPy, step by step, from
+                 the Theorem of Sec. II-D (the method Algorithm 1 runs), with the stopping and
                  status rules this project adopts where the paper is silent.
 * ``exact``    — the same iteration and the paper's closed forms (Corollaries
                  1, 2, 4, 6) in exact rational arithmetic (``fractions``), for
@@ -35,6 +35,6 @@ from .nn_fp64 import (  # noqa: F401
     X0_TRANSPOSE, X0_SCALED_IDENTITY, X0_GIVEN, X0_TRANSPOSE_FROB, X0_POWER_IDENTITY,
     X0_POWER_TRANSPOSE, X0_JACOBI, splitmix64, power_vector, theta2,
     norm_1, norm_inf, initial_guess, residual, rms_of, nn_step, nn_ref,
-    nn_solve_ref, nn_factorized_solve_ref, nn_cns_solve_ref, nn_batched_ref,
+    nn_solve_ref, nn_factorized_solve_ref, nn_cns_solve_ref,
 )
 from .nn_sparse import nn_sparse_solve_ref, sparse_preconditioner  # noqa: F401,E402

@@ -19,8 +19,9 @@ design notes of the repository):
   residual on the right, X * sum_n (I - A X)^n.  The two are equal in exact
   arithmetic because X (A X)^n = (X A)^n X; ``tests/test_oracle_exact.py``
   checks that equality in rational arithmetic.
-* Algorithm 1's "Trace(W)" is the scale 1/Tr(W) of the trace normalisation
-  (Sec. II-A), and its "1 - Z W" is I - Z W.
+* Algorithm 1 sets its scale to the trace of W itself and subtracts the
+  product from a scalar one; both are read as in Sec. II-A and the Theorem:
+  the scale is the trace normalisation 1/Tr(W), the residual is I - Z W.
 * Initial iterates.  ``X0_SCALED_IDENTITY`` is the paper's own choice
   phi^(0) = I with Theta = 1/Tr(W) (Sec. II-A, Sec. II-D), i.e.
   X_0 = I / Re Tr(A), for Hermitian positive definite A.
@@ -35,8 +36,8 @@ design notes of the repository):
   would tend to 1/lambda^2) and read here with plain norms (1/lambda_max);
   its random vector comes from SplitMix64 so that the device draws the same
   one; ``X0_JACOBI`` X_0 = diag(A)^-1, the diagonal preconditioner.
-* Accuracy measure.  rms = ||I - A X||_F / sqrt(N) ("root mean Frobenius
-  norm error", Sec. II).  The paper iterates a fixed number of nests; a
+* Accuracy measure.  rms = ||I - A X||_F / sqrt(N), the root-mean Frobenius
+  error of Sec. II divided by sqrt(N), not N.  The paper iterates a fixed number of nests; a
   tolerance stop on this rms, tested before each update, is our addition.
 * Status rules (the paper has none): see ``nn_ref``.
 """
@@ -201,18 +202,14 @@ def rms_of(R: np.ndarray) -> float:
 def nn_step(X: np.ndarray, R: np.ndarray, d: int) -> np.ndarray:
     """One nest, given the residual R = I - A X of the current iterate.
 
-    Algorithm 1: S = I + sum_{l=1..L} P^l with the powers built one product
-    at a time, then the iterate is multiplied by S (right form: X S).
-    That is d - 1 products for the powers R^2..R^d plus one for X S, which
-    with the residual product gives the L + 1 products per nest of the cost
-    model of Sec. II-D.
+    The Theorem of Sec. II-D in the right form: the next iterate is the
+    current one times the truncated Neumann polynomial of degree d in its own
+    residual, X_{k+1} = X_k * sum_{n=0..d} R^n.  The polynomial is summed
+    term by term as defined, every power R^n taken from
+    ``numpy.linalg.matrix_power`` (R^0 = I); no Horner form, no reuse of one
+    power for the next.
     """
-    n = R.shape[0]
-    S = np.eye(n, dtype=R.dtype)
-    P_l = None
-    for l in range(1, d + 1):
-        P_l = R.copy() if l == 1 else P_l @ R
-        S = S + P_l
+    S = sum(np.linalg.matrix_power(R, m) for m in range(d + 1))
     return X @ S
 
 
@@ -477,19 +474,3 @@ def nn_cns_solve_ref(A, B, d: int = 2, x0: int = X0_TRANSPOSE, nests: int = 1,
         x_prev, rel_prev = x, rel
         x = x + t
         T += 1
-
-
-def nn_batched_ref(mats, d: int = 2, x0: int = X0_TRANSPOSE, fixed_iter: int = 4):
-    """The batched form: each matrix of ``mats`` independently, fixed nests.
-
-    Returns (list of X, list of info).  Matrices are promoted to complex128
-    (or float64) before the iteration.
-    """
-    Xs, infos = [], []
-    for M in mats:
-        M = np.asarray(M)
-        M = M.astype(np.complex128 if np.iscomplexobj(M) else np.float64)
-        X, info = nn_ref(M, d=d, x0=x0, fixed_iter=fixed_iter)
-        Xs.append(X)
-        infos.append(info)
-    return Xs, infos

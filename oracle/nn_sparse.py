@@ -17,8 +17,8 @@ nests of depth L give for T = (L+1)^i - 1 (Corollary 2).  P is applied as
 P y = y - phi (W y): one sparse product per application.
 
 Readings (listed in the design notes):
-* Algorithm 2 prints Z = B first and multiplies by phi at the end; for a
-  scalar phi that is the same as starting from phi B.  For the diagonal
+* Algorithm 2 starts from B and applies phi at the end; for a scalar phi
+  that is the same as starting from phi B.  For the diagonal
   preconditioner (which does not commute with W) the series is taken in the
   form of Corollary 6, prod (I + P^(2^n)) phi B with P = I - phi W.
 * Control: the rules of the dense factorised solve, on the phi-weighted
@@ -86,9 +86,10 @@ def nn_sparse_solve_ref(indptr, indices, data, B, x0: int = X0_SCALED_IDENTITY,
     phi-weighted residual the rules use), "status", "trace" (control values
     after 0, 1, ... terms), "den"}.
 
-    fixed_terms = 2^s - 1: Algorithm 2's factorised loop, Z <- Z + P^(2^n) Z
-    for n < s with P^(2^n) Z formed by 2^n applications of P.  Other
-    fixed_terms: the series term by term, t_{m+1} = P t_m, x = sum t_m.
+    fixed_terms = 2^s - 1: the factorised form of Corollary 6 that Algorithm 2
+    evaluates, prod_{n<s} (I + P^(2^n)) phi B with each P^(2^n) y formed by
+    2^n applications of P.  Other fixed_terms: the series term by term,
+    t_{m+1} = P t_m, x = sum t_m.
     Tolerance mode (fixed_terms None): term by term, with the control value
     after each term and the rules of the dense factorised solve, at most
     max_terms terms.
@@ -128,15 +129,20 @@ def nn_sparse_solve_ref(indptr, indices, data, B, x0: int = X0_SCALED_IDENTITY,
         T = int(fixed_terms)
         s = (T + 1).bit_length() - 1
         if T >= 1 and (1 << s) == T + 1:
-            # Algorithm 2: Z = phi B; for k = 1, 2, 4, ..., 2^(s-1): Z = Z + P^k Z
-            Z = phiB.copy()
+            # Corollary 6's product form, the one Algorithm 2 evaluates:
+            # x = prod_{e<s} (I + P^(2^e)) phi B, each factor applied to the
+            # running product, its power P^(2^e) y formed as 2^e applications
+            # of P (no power of P is stored).
+            def apply_power(y, m):
+                for _ in range(m):
+                    y = apply_p(y)
+                return y
+
+            x = phiB.copy()
             for e in range(s):
-                Y = Z
-                for _ in range(1 << e):
-                    Y = apply_p(Y)
-                Z = Z + Y
-            x = Z
+                x = x + apply_power(x, 1 << e)
         else:
+            # the truncated series itself, sum_{m<=T} P^m phi B, term by term
             t = phiB.copy()
             x = t.copy()
             for _ in range(T):

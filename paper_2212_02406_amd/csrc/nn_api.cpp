@@ -171,6 +171,8 @@ nn_status finish_info(Ctl& c, nn_status st, int iters, double rms, int n_trace,
     c.info->iters = iters;
     c.info->rms = rms;
     c.info->gemms = c.gemms;
+    for (int i = 0; i < 3; ++i) c.info->prec_gemms[i] = 0;
+    c.info->prec_gemms[is_double(c.dt) ? 2 : 1] = c.gemms;
     c.info->n_trace = n_trace;
     for (int i = 0; i < n_trace && i < NN_TRACE_MAX; ++i) c.info->rms_trace[i] = trace[i];
     float ms = 0.f;
@@ -328,8 +330,15 @@ nn_status nn_create(nn_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-    c->num_cus = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    if (prop.multiProcessorCount > 0) c->num_cus = prop.multiProcessorCount;
+    // the architecture name up to its feature suffix ("gfx950:sramecc+:xnack-")
+    size_t i = 0;
+    for (; i + 1 < sizeof(c->arch) && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+      c->arch[i] = prop.gcnArchName[i];
+    c->arch[i] = 0;
+  }
+  if (!c->arch[0]) strcpy(c->arch, "unknown");
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * kHostSlots,
                     hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess) {

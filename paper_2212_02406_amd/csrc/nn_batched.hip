@@ -602,8 +602,34 @@ hipError_t launch_batched(const BatchedArgs& args, hipStream_t s) {
   return hipGetLastError();
 }
 
+size_t batched_static_lds() {
+  // The persistent kernels' own LDS (the reduction rows and the work item),
+  // as the compiler laid it out: 8720 bytes on gfx950 for every instantiation.
+  static size_t cached = 0;
+  if (!cached) {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&batched_nn<true, false>)) ==
+            hipSuccess &&
+        fa.sharedSizeBytes > 0)
+      cached = fa.sharedSizeBytes;
+    else
+      cached = sizeof(double) * kWaves * (8 + 2 * kMaxN) + 16;
+  }
+  return cached;
+}
+
+int batched_fit_wave_max_k(nn_dtype dt, int max_n, int wave_max_k, int depth) {
+  const bool cplx = dt == NN_C64;
+  int wk = wave_max_k < max_n ? wave_max_k : max_n;
+  const size_t cap = kBatchedLdsCu - batched_static_lds();
+  const size_t lim = cap < kBatchedDynLds ? cap : kBatchedDynLds;
+  // the one-wave sizes the kernel is tuned for, largest first
+  while (wk > 0 && lds_bytes(cplx, max_n, wk, depth) > lim) wk = wk > 16 ? 16 : wk > 8 ? 8 : 0;
+  return wk;
+}
+
 hipError_t batched_allow_lds() {
-  const int lim = 150 * 1024;  // dynamic part; the kernels' static LDS is under 10 KB
+  const int lim = (int)kBatchedDynLds;  // dynamic part; the static part is batched_static_lds()
   const void* kernels[4] = {reinterpret_cast<const void*>(&batched_nn<true, false>),
                             reinterpret_cast<const void*>(&batched_nn<true, true>),
                             reinterpret_cast<const void*>(&batched_nn<false, false>),

@@ -1,26 +1,34 @@
-// nn_batched.cpp — C ABI of the batched persistent inversion (see include/nn.h).
+// nn_batched_api.cpp — C ABI of the batched persistent inversion (see include/nn.h).
 //
 // A call enqueues two kernels (plan, persistent) that are captured once into
 // a HIP graph on a private stream and replayed on the caller's stream while
 // the arguments stay the same; the graph holds no memset node (the plan
 // kernel resets the work counter itself).  The kernel configuration
 // (matrices per wave threshold, workgroups per CU) comes from the context's
-// autotune table, filled by nn_batched_autotune, else from a default.
+// autotune table, filled by nn_batched_autotune (or read from the autotune
+// cache file named by NN_AUTOTUNE_CACHE), else from a default.  The one-wave
+// size limit is always clamped to what the LDS of one workgroup holds at the
+// call's depth.  NN_BATCHED_GRID (a positive integer) overrides the number of
+// persistent workgroups, for tests that make one workgroup process many work
+// items back to back.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "nn_internal.h"
 
 namespace nn {
 namespace {
 
-constexpr size_t kLdsPerCu = 160 * 1024;
-
 nn_status check_batched(nn_ctx* ctx, const void* A, const void* X, const int64_t* offsets,
                         const int32_t* sizes, int32_t batch, int32_t max_n, nn_dtype dt,
-                        const nn_params* p, void* ws, size_t ws_bytes) {
+                        const nn_params* p) {
   if (!ctx || !A || !X || !offsets || !sizes || batch < 1 || max_n < 1 || max_n > 64 || !p)
     return NN_ERR_ARG;
   if (A == X) return NN_ERR_ARG;
@@ -33,6 +41,10 @@ nn_status check_batched(nn_ctx* ctx, const void* A, const void* X, const int64_t
       (!(p->tol >= 0.0) || p->max_iter < 1 || p->max_iter > kBatchedMaxIter))
     return NN_ERR_ARG;
   if (p->prec != NN_PREC_PLAIN) return NN_ERR_UNSUPPORTED;
+  return NN_OK;
+}
+
+nn_status check_ws(int32_t batch, void* ws, size_t ws_bytes) {
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || ws_bytes < batched_ws_bytes(batch))
     return NN_ERR_WORKSPACE;
   return NN_OK;
@@ -63,9 +75,31 @@ void store(nn_ctx* ctx, const BatchedTune& t) {
   ctx->tune[0] = t;
 }
 
+// Workgroups of the persistent kernel one CU holds, from their LDS (dynamic
+// buffers plus the kernel's static LDS), at most 8.
 int max_wg_per_cu(nn_dtype dt, int max_n, int wave_max_k, int depth) {
-  const size_t lds = batched_lds_bytes(dt, max_n, wave_max_k, depth) + 4 * 1024;  // + static LDS
-  return std::max(1, (int)std::min<size_t>(8, kLdsPerCu / lds));
+  const size_t lds = batched_lds_bytes(dt, max_n, wave_max_k, depth) + batched_static_lds();
+  return std::max(1, (int)std::min<size_t>(8, kBatchedLdsCu / lds));
+}
+
+// NN_BATCHED_GRID: a forced number of persistent workgroups (0: none).
+int grid_override() {
+  const char* v = getenv("NN_BATCHED_GRID");
+  if (!v) return 0;
+  const long g = strtol(v, nullptr, 10);
+  return g > 0 && g <= (1 << 20) ? (int)g : 0;
+}
+
+// Kernel configuration of one launch: the one-wave size limit (fitted to the
+// LDS at this depth) and the persistent grid.
+void configure(nn_ctx* ctx, const BatchedTune& t, nn_dtype dt, int max_n, int depth, int batch,
+               int* wave_max_k, int* grid) {
+  const int wk = batched_fit_wave_max_k(dt, max_n, std::min({t.wave_max_k, max_n, 32}), depth);
+  const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(dt, max_n, wk, depth));
+  int g = std::max(1, std::min(batch, ctx->num_cus * per_cu));
+  if (const int o = grid_override()) g = std::min(o, batch);
+  *wave_max_k = wk;
+  *grid = g;
 }
 
 void drop_graph(nn_ctx* ctx) {
@@ -103,22 +137,18 @@ BatchedArgs args_of(const BatchedGraph& k) {
   return a;
 }
 
+hipError_t ensure_cap_stream(nn_ctx* ctx) {
+  if (ctx->cap_stream) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  return batched_allow_lds();
+}
+
 // Launch through the cached graph (capturing it first if the key changed).
 nn_status run_graph(nn_ctx* ctx, const BatchedGraph& key) {
-#ifdef NN_DIAG_NOGRAPH
-  if (!ctx->cap_stream) {
-    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) return NN_ERR_HIP;
-    if (batched_allow_lds() != hipSuccess) return NN_ERR_HIP;
-  }
-  return launch_batched(args_of(key), ctx->stream) == hipSuccess ? NN_OK : NN_ERR_HIP;
-#endif
   if (!same(ctx->bgraph, key)) {
     drop_graph(ctx);
-    if (!ctx->cap_stream) {
-      if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
-        return NN_ERR_HIP;
-      if (batched_allow_lds() != hipSuccess) return NN_ERR_HIP;
-    }
+    if (ensure_cap_stream(ctx) != hipSuccess) return NN_ERR_HIP;
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return NN_ERR_HIP;
@@ -159,13 +189,49 @@ BatchedGraph make_key(nn_ctx* ctx, const void* A, void* X, const int64_t* offset
   k.iters = p->fixed_iter;
   k.tol = p->fixed_iter > 0 ? 0.0 : p->tol;
   k.max_iter = p->fixed_iter > 0 ? 0 : p->max_iter;
-  k.wave_max_k = std::min({t.wave_max_k, max_n, 32});
-  const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(dt, max_n, k.wave_max_k, p->depth));
-  k.grid = std::max(1, std::min(batch, ctx->num_cus * per_cu));
-#ifdef NN_DIAG_GRID
-  k.grid = NN_DIAG_GRID;
-#endif
+  configure(ctx, t, dt, max_n, p->depth, batch, &k.wave_max_k, &k.grid);
   return k;
+}
+
+// ---- autotune cache file ----------------------------------------------------
+// One line per entry: "<arch> <dtype> <max_n> <wave_max_k> <wg_per_cu> <ms>",
+// keyed by (arch, dtype, max_n); later lines replace earlier ones.
+
+std::mutex g_cache_mu;
+
+const char* cache_path() {
+  const char* p = getenv("NN_AUTOTUNE_CACHE");
+  return p && *p ? p : nullptr;
+}
+
+bool cache_read(const char* path, const char* arch, nn_dtype dt, int max_n, BatchedTune* out,
+                float* ms) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char a[64];
+  int d, mn, wk, wg;
+  float t;
+  bool found = false;
+  while (fscanf(f, "%63s %d %d %d %d %f", a, &d, &mn, &wk, &wg, &t) == 6) {
+    if (strcmp(a, arch) == 0 && d == (int)dt && mn == max_n && wk >= 0 && wk <= 32 && wg >= 1 &&
+        wg <= 8) {
+      out->dtype = d;
+      out->max_n = mn;
+      out->wave_max_k = wk;
+      out->wg_per_cu = wg;
+      *ms = t;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_write(const char* path, const char* arch, const BatchedTune& t, float ms) {
+  FILE* f = fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation: an unwritable path only costs a re-tune
+  fprintf(f, "%s %d %d %d %d %.6f\n", arch, t.dtype, t.max_n, t.wave_max_k, t.wg_per_cu, ms);
+  fclose(f);
 }
 
 }  // namespace
@@ -176,9 +242,7 @@ BatchedGraph make_key(nn_ctx* ctx, const void* A, void* X, const int64_t* offset
 // size only; the arithmetic is the same on either path.
 hipError_t launch_batched_direct(nn_ctx* ctx, BatchedArgs a, hipStream_t s) {
   const BatchedTune t = lookup(ctx, a.dt, 64);
-  a.wave_max_k = std::min({t.wave_max_k, a.max_n, 32});
-  const int per_cu = std::min(t.wg_per_cu, max_wg_per_cu(a.dt, a.max_n, a.wave_max_k, a.depth));
-  a.grid = std::max(1, std::min(a.batch, ctx->num_cus * per_cu));
+  configure(ctx, t, a.dt, a.max_n, a.depth, a.batch, &a.wave_max_k, &a.grid);
   return launch_batched(a, s);
 }
 
@@ -197,9 +261,9 @@ nn_status nn_invert_batched(nn_ctx* ctx, const void* A_packed, void* X_packed,
                             const int64_t* offsets, const int32_t* sizes, int32_t batch,
                             int32_t max_n, nn_dtype dtype, const nn_params* params, void* ws,
                             size_t ws_bytes, nn_info_dev* per_matrix) {
-  nn_status v = check_batched(ctx, A_packed, X_packed, offsets, sizes, batch, max_n, dtype, params,
-                              ws, ws_bytes);
+  nn_status v = check_batched(ctx, A_packed, X_packed, offsets, sizes, batch, max_n, dtype, params);
   if (v != NN_OK) return v;
+  if ((v = check_ws(batch, ws, ws_bytes)) != NN_OK) return v;
   if (hipSetDevice(ctx->device) != hipSuccess) return NN_ERR_HIP;
   const BatchedTune t = lookup(ctx, dtype, max_n);
   return run_graph(ctx, make_key(ctx, A_packed, X_packed, offsets, sizes, batch, max_n, dtype,
@@ -209,16 +273,33 @@ nn_status nn_invert_batched(nn_ctx* ctx, const void* A_packed, void* X_packed,
 nn_status nn_batched_autotune(nn_ctx* ctx, const void* A_packed, void* X_packed,
                               const int64_t* offsets, const int32_t* sizes, int32_t batch,
                               int32_t max_n, nn_dtype dtype, const nn_params* params, void* ws,
-                              size_t ws_bytes, float* best_ms) {
-  nn_status v = check_batched(ctx, A_packed, X_packed, offsets, sizes, batch, max_n, dtype, params,
-                              ws, ws_bytes);
+                              size_t ws_bytes, float* best_ms, int32_t* from_cache) {
+  nn_status v = check_batched(ctx, A_packed, X_packed, offsets, sizes, batch, max_n, dtype, params);
   if (v != NN_OK) return v;
+  if ((v = check_ws(batch, ws, ws_bytes)) != NN_OK) return v;
+  if (from_cache) *from_cache = 0;
+  const char* path = cache_path();
+  if (path) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    BatchedTune c;
+    float ms = 0.f;
+    if (cache_read(path, ctx->arch, dtype, max_n, &c, &ms)) {
+      store(ctx, c);
+      if (best_ms) *best_ms = ms;
+      if (from_cache) *from_cache = 1;
+      return NN_OK;
+    }
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return NN_ERR_HIP;
+  if (ensure_cap_stream(ctx) != hipSuccess) return NN_ERR_HIP;
   const int waves[] = {0, 8, 16, 32};
   BatchedTune best = lookup(ctx, dtype, max_n);
   float best_t = INFINITY;
+  std::vector<std::pair<int, int>> seen;  // (fitted wave_max_k, grid) already timed
   for (int wk : waves) {
     if (wk > max_n) continue;
+    const int fit = batched_fit_wave_max_k(dtype, max_n, wk, params->depth);
+    if (fit != wk) continue;  // does not fit the LDS at this depth
     const int cap = max_wg_per_cu(dtype, max_n, wk, params->depth);
     for (int per_cu = 1; per_cu <= cap; per_cu *= 2) {
       BatchedTune t;
@@ -228,6 +309,10 @@ nn_status nn_batched_autotune(nn_ctx* ctx, const void* A_packed, void* X_packed,
       t.wg_per_cu = per_cu;
       const BatchedGraph key = make_key(ctx, A_packed, X_packed, offsets, sizes, batch, max_n,
                                         dtype, params, ws, nullptr, t);
+      if (std::find(seen.begin(), seen.end(), std::make_pair(key.wave_max_k, key.grid)) !=
+          seen.end())
+        continue;  // the same launch as a candidate already timed
+      seen.emplace_back(key.wave_max_k, key.grid);
       float ms_min = INFINITY;
       for (int rep = 0; rep < 3; ++rep) {
         if (hipEventRecord(ctx->ev_start, ctx->stream) != hipSuccess) return NN_ERR_HIP;
@@ -248,6 +333,10 @@ nn_status nn_batched_autotune(nn_ctx* ctx, const void* A_packed, void* X_packed,
   }
   store(ctx, best);
   if (best_ms) *best_ms = best_t;
+  if (path && isfinite(best_t)) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    cache_write(path, ctx->arch, best, best_t);
+  }
   return NN_OK;
 }
 
@@ -272,6 +361,13 @@ nn_status nn_batched_set_config(nn_ctx* ctx, nn_dtype dtype, int32_t max_n, int3
   t.wg_per_cu = wg_per_cu;
   store(ctx, t);
   return NN_OK;
+}
+
+int32_t nn_batched_fit_config(nn_dtype dtype, int32_t max_n, int32_t wave_max_k, int32_t depth) {
+  if (max_n < 1 || max_n > 64 || wave_max_k < 0 || wave_max_k > 32 || depth < 1 ||
+      depth > NN_MAX_DEPTH || (dtype != NN_C64 && dtype != NN_F32))
+    return -1;
+  return batched_fit_wave_max_k(dtype, max_n, wave_max_k, depth);
 }
 
 }  // extern "C"

@@ -166,6 +166,8 @@ nn_status nn_solve_cns(nn_ctx* ctx, const void* A, int64_t lda, const void* B, i
       info->iters = terms;
       info->rms = rel;
       info->gemms = gemms;
+      for (int i = 0; i < 3; ++i) info->prec_gemms[i] = 0;
+      info->prec_gemms[is_double(dt) ? 2 : 1] = gemms;
       info->n_trace = n_trace;
       for (int i = 0; i < n_trace; ++i) info->rms_trace[i] = trace[i];
       float ms = 0.f;

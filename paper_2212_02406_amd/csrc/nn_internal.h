@@ -150,6 +150,16 @@ hipError_t launch_sumsq(const void* src, bool f64, int64_t ld, int64_t rows, int
 size_t batched_ws_bytes(int32_t batch);
 size_t batched_lds_bytes(nn_dtype dt, int max_n, int wave_max_k, int depth);
 hipError_t batched_allow_lds();  // raise the dynamic LDS limit (call outside capture)
+// LDS of one CU, and the dynamic LDS limit the batched kernels are given.
+constexpr size_t kBatchedLdsCu = 160 * 1024;
+constexpr size_t kBatchedDynLds = 150 * 1024;
+// Static LDS of the persistent kernel (from the compiled kernel's attributes).
+size_t batched_static_lds();
+// The largest one-wave size limit <= wave_max_k (stepping 32 -> 16 -> 8 -> 0)
+// whose LDS fits one workgroup: dynamic part <= kBatchedDynLds and dynamic +
+// static <= kBatchedLdsCu.  (Complex matrices at depth >= 3 with one-wave
+// matrices up to 32 would need 204 KB.)
+int batched_fit_wave_max_k(nn_dtype dt, int max_n, int wave_max_k, int depth);
 // Arguments of one batched launch.  Matrix b: A at element offset offsets[b],
 // X at xoffsets[b] (offsets if null), size sizes[b].  iters > 0: exactly that
 // many nests; iters == 0: tolerance mode with tols[b] (tol if null) and
@@ -226,6 +236,7 @@ constexpr int kTuneSlots = 8;
 struct nn_ctx {
   int device = 0;
   int num_cus = 256;
+  char arch[64] = {0};  // gcnArchName of the device (autotune cache key)
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
   double* host = nullptr;            // pinned read-back slots

@@ -144,6 +144,7 @@ struct Run {
   int64_t n;
   int d;
   int gemms = 0;
+  int prec_gemms[3] = {0, 0, 0};  // BF16, FP32, FP64 products
   int n_trace = 0;
   double trace[NN_TRACE_MAX];
   hipStream_t s() const { return ctx->stream; }
@@ -171,10 +172,12 @@ hipError_t plain_update(Run& r, Elem e, const GemmPlan& plan, const T* X, int64_
     hipError_t err = launch_gemm(e, false, plan, g, r.s());
     if (err != hipSuccess) return err;
     ++r.gemms;
+    ++r.prec_gemms[sizeof(T) == 8 ? 2 : 1];
     Ucur = Un;
   }
   GemmArgs g{X, ldx, Ucur, n, Xn, ldxn, X, ldx, n, n, n, 1.0, 0.0, nullptr};
   ++r.gemms;
+  ++r.prec_gemms[sizeof(T) == 8 ? 2 : 1];
   return launch_gemm(e, false, plan, g, r.s());
 }
 
@@ -224,6 +227,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
       info->n_trace = r.n_trace;
       for (int i = 0; i < r.n_trace; ++i) info->rms_trace[i] = r.trace[i];
       for (int i = 0; i < 3; ++i) info->phase_iters[i] = phase_it[i];
+      for (int i = 0; i < 3; ++i) info->prec_gemms[i] = r.prec_gemms[i];
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop) == hipSuccess) info->device_ms = ms;
     }
@@ -249,6 +253,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
                      w.R32, n, w.Rbf, w.ldb, w.RbfT, w.ldb, w.part};
       HIP_TRY(launch_gemm_bf16(pb, g, s));
       ++r.gemms;
+      ++r.prec_gemms[0];
       HIP_TRY(launch_rms_reduce(w.part, pb.num_tiles(), n, w.scal + 2, s));
       HIP_TRY(r.fetch(w.scal + 2, 1));
       const double rms = ctx->host[0];
@@ -263,6 +268,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
                        nullptr, 0, nullptr, 0, UTn, w.ldb, nullptr};
         HIP_TRY(launch_gemm_bf16(pb, h, s));
         ++r.gemms;
+        ++r.prec_gemms[0];
         UT = UTn;
       }
       // X' = X + X U (FP32 master), BF16 copies of X' for the next nest, ||X'||_F
@@ -271,6 +277,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
                      w.X32[nx], n, w.Xbf[nx], w.ldb, w.XbfT[nx], w.ldb, w.part};
       HIP_TRY(launch_gemm_bf16(pb, u, s));
       ++r.gemms;
+      ++r.prec_gemms[0];
       HIP_TRY(launch_rms_reduce(w.part, pb.num_tiles(), 1, w.scal + 3, s));
       HIP_TRY(r.fetch(w.scal + 3, 1));
       xnorm = ctx->host[0];
@@ -288,6 +295,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
     GemmArgs g{w.A32, n, w.X32[cur], n, w.R32, n, nullptr, 0, n, n, n, -1.0, 1.0, w.part};
     HIP_TRY(launch_gemm(Elem::F32, false, p32, g, s));
     ++r.gemms;
+    ++r.prec_gemms[1];
     HIP_TRY(launch_rms_reduce(w.part, p32.num_tiles(), n, w.scal + 2, s));
     HIP_TRY(r.fetch(w.scal + 2, 1));
     const double rms = ctx->host[0];
@@ -337,6 +345,7 @@ nn_status run_mixed(nn_ctx* ctx, const void* Av, int64_t lda, void* Xv, int64_t 
     GemmArgs g{A, lda, Xc, ldc, w.R64, n, nullptr, 0, n, n, n, -1.0, 1.0, w.part};
     HIP_TRY(launch_gemm(Elem::F64, false, p64, g, s));
     ++r.gemms;
+    ++r.prec_gemms[2];
     HIP_TRY(launch_rms_reduce(w.part, p64.num_tiles(), n, w.scal + 2, s));
     HIP_TRY(r.fetch(w.scal + 2, 1));
     const double rms = ctx->host[0];

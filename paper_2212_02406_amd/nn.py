@@ -56,12 +56,13 @@ class nn_info(ctypes.Structure):
                 ("device_ms", ctypes.c_float), ("gemm_ms", ctypes.c_float),
                 ("gemms", ctypes.c_int32),
                 ("n_trace", ctypes.c_int32), ("phase_iters", ctypes.c_int32 * 3),
+                ("prec_gemms", ctypes.c_int32 * 3),
                 ("rms_trace", ctypes.c_double * NN_TRACE_MAX)]
 
     def as_dict(self):
         return {"iters": self.iters, "status": self.status, "rms": self.rms,
                 "device_ms": self.device_ms, "gemm_ms": self.gemm_ms, "gemms": self.gemms,
-                "phase_iters": list(self.phase_iters),
+                "phase_iters": list(self.phase_iters), "prec_gemms": list(self.prec_gemms),
                 "trace": [self.rms_trace[i] for i in range(self.n_trace)]}
 
 
@@ -134,7 +135,9 @@ _SIGS = {
     "nn_invert_batched": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
                                          _sz, _p]),
     "nn_batched_autotune": (ctypes.c_int, [_p, _p, _p, _p, _p, _i32, _i32, ctypes.c_int, _PP, _p,
-                                           _sz, ctypes.POINTER(ctypes.c_float)]),
+                                           _sz, ctypes.POINTER(ctypes.c_float),
+                                           ctypes.POINTER(_i32)]),
+    "nn_batched_fit_config": (_i32, [ctypes.c_int, _i32, _i32, _i32]),
     "nn_batched_get_config": (ctypes.c_int, [_p, ctypes.c_int, _i32, ctypes.POINTER(_i32),
                                              ctypes.POINTER(_i32)]),
     "nn_batched_set_config": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32]),
@@ -512,8 +515,10 @@ def invert_batched(packed, offsets, sizes, max_n, depth=2, x0="transpose", fixed
 
 
 def batched_autotune(packed, offsets, sizes, max_n, depth=2, x0="transpose", fixed_iter=4,
-                     ctx: Context | None = None):
-    """nn_batched_autotune; returns (best_ms, wave_max_k, wg_per_cu)."""
+                     ctx: Context | None = None, with_source=False):
+    """nn_batched_autotune; returns (best_ms, wave_max_k, wg_per_cu), plus
+    whether the configuration came from the NN_AUTOTUNE_CACHE file when
+    with_source is set."""
     torch = _torch()
     batch = int(sizes.numel())
     dt = dtype_code(packed)
@@ -522,15 +527,18 @@ def batched_autotune(packed, offsets, sizes, max_n, depth=2, x0="transpose", fix
     ctx = ctx or default_context(packed.device.index or 0)
     hold, ws_ptr, ws_bytes = workspace(nn_batched_workspace_size(batch, dt), packed.device)
     best = ctypes.c_float(0.0)
+    cached = ctypes.c_int32(0)
     st = nn_batched_autotune(ctx.ptr, ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                              ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(sizes.data_ptr()),
                              batch, int(max_n), dt, ctypes.byref(prm), ctypes.c_void_p(ws_ptr),
-                             ws_bytes, ctypes.byref(best))
+                             ws_bytes, ctypes.byref(best), ctypes.byref(cached))
     if st != NN_OK:
         raise NNError(st, "nn_batched_autotune")
     wk, wg = ctypes.c_int32(), ctypes.c_int32()
     nn_batched_get_config(ctx.ptr, dt, int(max_n), ctypes.byref(wk), ctypes.byref(wg))
     del hold
+    if with_source:
+        return best.value, wk.value, wg.value, bool(cached.value)
     return best.value, wk.value, wg.value
 
 

@@ -27,11 +27,42 @@ def test_exports_every_declared_symbol():
         assert hasattr(raw, name), name
 
 
+def test_struct_layout_matches_c_compiler():
+    """Every field offset and struct size of the binding equals what gcc
+    computes from include/nn.h (offsetof / sizeof in a generated C file)."""
+    import shutil
+    import subprocess
+    import tempfile
+    nn = _nn()
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [nn.nn_params, nn.nn_info, nn.nn_info_dev, nn.nn_cns_params, nn.nn_sparse_params,
+               nn.nn_server_params, nn.nn_request_info, nn.nn_server_stats]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nn.h"', "int main(void) {"]
+    expect = []
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("%zu\\n", sizeof({name}));')
+        expect.append(ctypes.sizeof(st))
+        for field, _ in st._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({name}, {field}));')
+            expect.append(getattr(st, field).offset)
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as td:
+        src, exe = os.path.join(td, "layout.c"), os.path.join(td, "layout")
+        open(src, "w").write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe],
+                       check=True)
+        got = [int(x) for x in subprocess.run([exe], check=True, capture_output=True,
+                                               text=True).stdout.split()]
+    assert got == expect
+
+
 def test_struct_layout():
     nn = _nn()
     assert ctypes.sizeof(nn.nn_params) == 40 and nn.nn_params.power_k.offset == 32
-    assert nn.nn_info.rms_trace.offset == 48
-    assert ctypes.sizeof(nn.nn_info) == 48 + 8 * nn.NN_TRACE_MAX
+    assert nn.nn_info.prec_gemms.offset == 44 and nn.nn_info.rms_trace.offset == 56
+    assert ctypes.sizeof(nn.nn_info) == 56 + 8 * nn.NN_TRACE_MAX
     assert ctypes.sizeof(nn.nn_info_dev) == 16
     assert ctypes.sizeof(nn.nn_server_params) == 32 and nn.nn_server_params.power_k.offset == 24
     assert ctypes.sizeof(nn.nn_request_info) == 64
@@ -155,3 +186,39 @@ def test_create_without_gpu_reports_hip_error():
     c = ctypes.c_void_p()
     assert nn.nn_create(ctypes.byref(c), 0, None) in (nn.NN_ERR_HIP, nn.NN_ERR_ARG)
     assert nn.nn_create(None, 0, None) == nn.NN_ERR_ARG
+
+
+def test_batched_one_wave_limit_fits_lds():
+    """nn_batched_fit_config lowers the one-wave size limit until the LDS of
+    one workgroup holds the matrices at the given depth.  The expected value
+    is recomputed here from the layout the batched kernel documents: a K x K
+    matrix buffer has pad16(K) rows of pad16(K or 2K real columns) + 4 floats;
+    two buffers per matrix (three from depth 3); a workgroup holds one matrix
+    of max_n or eight one-wave matrices; the kernel's static LDS is 8720
+    bytes; limits 150 KB dynamic, 160 KB per CU."""
+    nn = _nn()
+
+    def pad(x):
+        return (x + 15) // 16 * 16
+
+    def lds(cplx, max_n, wk, depth):
+        buf = lambda k: pad(k) * (pad(2 * k if cplx else k) + 4)  # noqa: E731
+        nb = 3 if depth >= 3 else 2
+        return 4 * max(nb * buf(max_n), 8 * nb * buf(max(wk, 1)))
+
+    lim = min(150 * 1024, 160 * 1024 - 8720)
+    for dt, cplx in ((nn.NN_C64, True), (nn.NN_F32, False)):
+        for depth in (1, 2, 3, 5, 8):
+            for max_n in (1, 8, 16, 33, 64):
+                for wk in (0, 5, 8, 16, 24, 32):
+                    w = min(wk, max_n)
+                    while w > 0 and lds(cplx, max_n, w, depth) > lim:
+                        w = 16 if w > 16 else 8 if w > 8 else 0
+                    assert nn.nn_batched_fit_config(dt, max_n, wk, depth) == w, (dt, depth, max_n, wk)
+    assert nn.nn_batched_fit_config(nn.NN_C64, 64, 32, 3) == 16   # 204 KB would not fit
+    assert nn.nn_batched_fit_config(nn.NN_C64, 64, 32, 2) == 32
+    assert nn.nn_batched_fit_config(nn.NN_F32, 64, 32, 8) == 32
+    assert nn.nn_batched_fit_config(nn.NN_F64, 64, 32, 2) == -1
+    assert nn.nn_batched_fit_config(nn.NN_C64, 65, 32, 2) == -1
+    assert nn.nn_batched_fit_config(nn.NN_C64, 64, 33, 2) == -1
+    assert nn.nn_batched_fit_config(nn.NN_C64, 64, 16, 0) == -1

@@ -318,3 +318,115 @@ def test_tolerance_mode_alone_vs_in_mix_bitwise():
         K = mats[b].shape[0]
         assert np.array_equal(X1, X[offsets[b]:offsets[b] + K * K]), b
         assert it1[0] == it[b] and rms1[0] == rms[b]
+
+
+# ---- one workgroup over many items, LDS fitting, persisted autotune --------
+
+@pytest.mark.parametrize("x0", ["transpose", "identity"])
+def test_one_workgroup_processes_every_item(x0, monkeypatch):
+    """NN_BATCHED_GRID=1: a single persistent workgroup takes all 512 MIMO
+    matrices back to back (group items, then wave items after them, on the
+    same LDS); every matrix against the oracle, and bitwise equal to the
+    default grid."""
+    _say(f"one workgroup, 512 mimo, x0={x0}")
+    packed, offsets, sizes, mats = W.mimo_gram_batch(batch=512, seed=3)
+    nn.batched_set_config(nn.NN_C64, 64, 16, 1)
+    Xref, _ = _run(packed, offsets, sizes, 64, depth=2, x0=x0, fixed_iter=4)
+    monkeypatch.setenv("NN_BATCHED_GRID", "1")
+    X, info = _run(packed, offsets, sizes, 64, depth=2, x0=x0, fixed_iter=4)
+    monkeypatch.delenv("NN_BATCHED_GRID")
+    _check(mats, offsets, X, info, 2, x0, 4)
+    assert np.array_equal(X, Xref)
+
+
+@pytest.mark.parametrize("grid", [1, 3])
+def test_small_grids_tolerance_mode_bitwise(grid, monkeypatch):
+    """The tolerance-mode kernel on one and three workgroups: the same bits as
+    the default grid for every matrix (K = 8..64, wave and group items)."""
+    _say(f"tolerance mode grid={grid}")
+    packed, offsets, sizes, mats = W.mimo_gram_batch(batch=256, seed=35)
+    Xref, iref = _run(packed, offsets, sizes, 64, fixed_iter=0, tol=1e-5, max_iter=30)
+    monkeypatch.setenv("NN_BATCHED_GRID", str(grid))
+    X, info = _run(packed, offsets, sizes, 64, fixed_iter=0, tol=1e-5, max_iter=30)
+    monkeypatch.delenv("NN_BATCHED_GRID")
+    assert np.array_equal(X, Xref)
+    for a, b in zip(info, iref):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_depth3_with_wave_max_k_32(cplx):
+    """Depth 3 keeps three LDS buffers per matrix; a configured one-wave limit
+    of 32 is lowered to what fits (16 for complex64: 32 would need 204 KB of
+    LDS), and the results match the oracle and the default configuration."""
+    _say(f"depth 3 wave_max_k=32 complex={cplx}")
+    dt = nn.NN_C64 if cplx else nn.NN_F32
+    if cplx:
+        packed, offsets, sizes, mats = W.mimo_gram_batch(batch=128, seed=36)
+    else:
+        szs = [int(k) for k in np.random.default_rng(36).choice([8, 16, 24, 32, 48, 64], 96)]
+        packed, offsets, sizes, mats = W.ragged_batch(szs, seed=36, lo=1.0, hi=20.0,
+                                                     complex_=False, dtype=np.float32)
+    assert nn.nn_batched_fit_config(dt, 64, 32, 3) == (16 if cplx else 32)
+    nn.batched_set_config(dt, 64, 16, 1)
+    Xref, _ = _run(packed, offsets, sizes, 64, depth=3, fixed_iter=3)
+    nn.batched_set_config(dt, 64, 32, 2)
+    X, info = _run(packed, offsets, sizes, 64, depth=3, fixed_iter=3)
+    nn.batched_set_config(dt, 64, 16, 1)
+    _check(mats, offsets, X, info, 3, "transpose", 3)
+    assert np.array_equal(X, Xref)
+
+
+def test_autotune_depth3_complex():
+    """The autotuner skips the candidates whose LDS does not fit at depth 3
+    (complex64, one-wave limit 32) instead of failing."""
+    _say("autotune depth 3")
+    packed, offsets, sizes, mats = W.mimo_gram_batch(batch=256, seed=37)
+    P, O, S = _upload(packed, offsets, sizes)
+    best_ms, wk, wg = nn.batched_autotune(P, O, S, 64, depth=3, fixed_iter=3)
+    assert best_ms > 0 and wk in (0, 8, 16)
+    X, info = nn.invert_batched(P, O, S, 64, depth=3, fixed_iter=3)
+    torch.cuda.synchronize()
+    _check(mats, offsets, X.cpu().numpy(), nn.decode_batched_info(info), 3, "transpose", 3,
+           sample=range(0, 256, 5))
+    nn.batched_set_config(nn.NN_C64, 64, 16, 1)
+
+
+_CACHE_CHILD = r"""
+import sys, json, torch
+sys.path.insert(0, sys.argv[1])
+from paper_2212_02406_amd import nn, workloads as W
+packed, offsets, sizes, mats = W.mimo_gram_batch(batch=384, seed=38)
+P, O, S = (torch.from_numpy(a).to('cuda:0') for a in (packed, offsets, sizes))
+best, wk, wg, cached = nn.batched_autotune(P, O, S, 64, fixed_iter=4, with_source=True)
+X, _ = nn.invert_batched(P, O, S, 64, fixed_iter=4)
+torch.cuda.synchronize()
+torch.save(X.cpu(), sys.argv[2])
+print(json.dumps({"best": best, "wk": wk, "wg": wg, "cached": cached}), flush=True)
+"""
+
+
+def test_autotune_cache_persists_across_processes(tmp_path):
+    """A second process finds the first one's entry in NN_AUTOTUNE_CACHE,
+    skips the timing runs, uses the same configuration and gives the same
+    bits."""
+    import json
+    import os
+    import subprocess
+    _say("autotune cache across processes")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, NN_AUTOTUNE_CACHE=str(tmp_path / "tune.txt"))
+    outs = []
+    for i in range(2):
+        r = subprocess.run([sys.executable, "-c", _CACHE_CHILD, root, str(tmp_path / f"x{i}.pt")],
+                           env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    assert not outs[0]["cached"] and outs[1]["cached"]
+    assert (outs[0]["wk"], outs[0]["wg"]) == (outs[1]["wk"], outs[1]["wg"])
+    assert abs(outs[0]["best"] - outs[1]["best"]) < 1e-3
+    lines = open(tmp_path / "tune.txt").read().split()
+    assert len(lines) == 6  # one entry, written once
+    x0 = torch.load(tmp_path / "x0.pt")
+    x1 = torch.load(tmp_path / "x1.pt")
+    assert torch.equal(x0, x1)
