@@ -1,7 +1,7 @@
 """Benchmark of the NN inversion on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--no-extras | --legs fp32,factorized,cns,starts,sparse,batched,mixed,serving]
+                    [--no-extras | --legs small,fp32,factorized,cns,starts,sparse,batched,mixed,serving]
 
 A step is one whole inversion through the C ABI: start-iterate prologue, then
 nests of d + 1 GEMMs until rms = ||I - A X||_F / sqrt(N) < tol.  The headline
@@ -15,6 +15,9 @@ stream during the timed steps, against the FP64 MFMA peak; HBM traffic per
 launch from the committed counter summary when it was taken on the current
 GEMM source), the oracle timed on the host on a bounded sample, and under
 "extra" the other workloads:
+  small    dense SPD N=256 FP64 at depths 1, 2, 3 from both starts: us per
+           inverse and per nest, GEMMs to 1e-12, the oracle at 1 and all
+           host threads;
   fp32     the headline matrix in FP32 (runs to its rounding floor);
   batched  4096 complex64 massive-MIMO Gram matrices, one graph launch;
   mixed    N=16384 cond 1e4: BF16/FP32/FP64 schedule vs plain FP64 at the
@@ -57,7 +60,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--legs", default="fp32,factorized,cns,starts,sparse,batched,mixed,serving",
+    ap.add_argument("--legs", default="small,fp32,factorized,cns,starts,sparse,batched,mixed,serving",
                     help="comma list of extra workloads to run")
     ap.add_argument("--mixed-n", type=int, default=16384)
     ap.add_argument("--serve-pool", type=int, default=64)
@@ -164,6 +167,95 @@ def cpu_baseline(A_h, depth, tol, gpu_iters):
                        f"final rms {info['rms']:.3e}, {t:.1f} s; host '{model}', {ncpu} logical "
                        f"CPUs, BLAS threads {threads}"),
             "host_cpu_model": model, "seconds": t, "iters": info["iters"]}
+
+
+def leg_small(nn, torch, workloads, np, n=256, reps=200, oracle_reps=5):
+    """The small single-matrix workload: dense SPD N=256, spectrum uniform in
+    [1, 100] (seed 1), FP64, depths 1, 2, 3, from the transpose start and
+    from I / Tr A, each to rms < 1e-12.  Per (depth, start): microseconds per
+    inverse through nn_invert's tolerance mode (one host read per nest) and,
+    where the device-stop mode exists, with the stopping rules on the device;
+    microseconds per nest from two fixed-nest runs (no host reads); GEMMs to
+    the tolerance, the measured form of the optimal-depth comparison
+    (Appendix 6); the GEMM launch time against the FP64 MFMA peak; and the
+    oracle on the host at one BLAS thread and at all of them."""
+    import oracle
+    A_h = workloads.dense_spd(n, 1.0, 100.0, 1)
+    A = torch.from_numpy(A_h).cuda()
+    X = torch.empty_like(A)
+    out = {"workload": (f"dense SPD N={n} FP64, spectrum uniform [1,100] (seed 1), tol rms 1e-12; "
+                        f"GPU: mean of {reps} inversions; oracle: mean of {oracle_reps}")}
+    flop = 2.0 * n ** 3
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        threadpool_limits = None
+    dev_stop = getattr(nn, "NN_FLAG_DEVICE_STOP", None)
+
+    def per_inverse(**kw):
+        for _ in range(5):
+            nn.invert(A, X=X, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, info = nn.invert(A, X=X, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e6, info
+
+    for x0 in ("transpose", "identity"):
+        for d in (1, 2, 3):
+            kw = dict(depth=d, x0=x0, tol=1e-12, max_iter=100)
+            us, info = per_inverse(**kw)
+            rec = {"us_per_inverse": us, "inverses_per_s": 1e6 / us, "nests": info["iters"],
+                   "gemms": info["gemms"], "rms": info["rms"], "status": info["status"],
+                   "flop_to_tol": info["gemms"] * flop}
+            if dev_stop is not None:
+                us_d, info_d = per_inverse(flags=dev_stop, **kw)
+                rec.update(us_per_inverse_device_stop=us_d, device_stop_nests=info_d["iters"],
+                           device_stop_status=info_d["status"],
+                           device_stop_rms=info_d["rms"])
+            # per nest: two fixed-nest runs, no host reads in between
+            f = {}
+            for k in (2, 12):
+                for _ in range(3):
+                    nn.invert(A, X=X, depth=d, x0=x0, fixed_iter=k)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps // 4):
+                    nn.invert(A, X=X, depth=d, x0=x0, fixed_iter=k)
+                torch.cuda.synchronize()
+                f[k] = (time.perf_counter() - t0) / (reps // 4) * 1e6
+            rec["us_per_nest_fixed"] = (f[12] - f[2]) / 10.0
+            # GEMM launch time from HIP events on the library's stream
+            _, it = nn.invert(A, X=X, flags=nn.NN_FLAG_TIME_GEMMS, **kw)
+            g_us = it["gemm_ms"] * 1e3 / it["gemms"]
+            rec["gemm_us_per_launch"] = g_us
+            rec["gemm_frac_fp64_mfma_peak"] = flop / (g_us * 1e-6) / 1e12 / PEAK_TFLOPS["f64"]
+            rec["whole_job_frac_fp64_mfma_peak"] = (rec["flop_to_tol"] / (us * 1e-6) / 1e12 /
+                                                    PEAK_TFLOPS["f64"])
+            # the oracle on the host, one BLAS thread and all of them
+            xo = oracle.X0_TRANSPOSE if x0 == "transpose" else oracle.X0_SCALED_IDENTITY
+            for label, lim in (("oracle_1_thread", 1), ("oracle_all_threads", None)):
+                ctxm = threadpool_limits(lim) if (threadpool_limits and lim) else None
+                try:
+                    if ctxm is not None:
+                        ctxm.__enter__()
+                    t0 = time.perf_counter()
+                    for _ in range(oracle_reps):
+                        _, io = oracle.nn_ref(A_h, d=d, x0=xo, tol=1e-12, max_iter=100)
+                    t = (time.perf_counter() - t0) / oracle_reps
+                finally:
+                    if ctxm is not None:
+                        ctxm.__exit__(None, None, None)
+                rec[label] = {"us_per_inverse": t * 1e6, "nests": io["iters"]}
+            out[f"{x0}_d{d}"] = rec
+            log(f"small N={n} {x0} d={d}: {rec}")
+    for x0 in ("transpose", "identity"):
+        g = {d: out[f"{x0}_d{d}"]["gemms"] for d in (1, 2, 3)}
+        out[f"{x0}_fewest_gemms_depth"] = min(g, key=lambda d: (g[d], d))
+    _, cpu_n, threads = host_cpu()
+    out["host_threads"] = threads
+    return out
 
 
 def leg_batched(nn, torch, workloads, np):
@@ -585,6 +677,8 @@ def main():
 
     extra = {}
     legs = set() if args.no_extras else set(args.legs.split(","))
+    if "small" in legs:
+        extra["small"] = leg_small(nn, torch, workloads, np)
     if "fp32" in legs:
         A32 = A.to(torch.float32)
         X32, i32, s32 = time_inversions(nn, torch, A32, 1, 1, depth=d, x0="transpose", tol=1e-6,

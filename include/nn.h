@@ -100,6 +100,18 @@ typedef enum {
 /* nn_params.flags bit: time every GEMM launch with a pair of HIP events on
    the context stream and report their sum in nn_info.gemm_ms. */
 #define NN_FLAG_TIME_GEMMS 1
+/* nn_params.flags bit (plain tolerance mode of nn_invert and nn_solve; no
+   effect in fixed mode or with NN_PREC_MIXED): the stopping rules run on the
+   device after every residual, in the same order and arithmetic as the host
+   rules, so X, status, iters, rms and the trace are the same as without the
+   flag.  A kernel holds the outcome in a device flag that turns every later
+   product of the call into a no-op, and the host reads it only every few
+   nests: as many nests as an rms falling at order d + 1 would still need
+   (rms_{k+1} >= rms_k^(d+1) holds for a normal residual), at most 16, so the
+   GPU runs ahead of the host instead of waiting for one read per nest.  Also
+   the start scale is checked on the device.  info->gemms counts the products
+   that did work. */
+#define NN_FLAG_DEVICE_STOP 2
 
 typedef struct {
   int32_t depth;      /* inception depth d, 1 <= d <= NN_MAX_DEPTH */
@@ -109,7 +121,8 @@ typedef struct {
   int32_t fixed_iter; /* > 0: exactly this many nests, no host sync, tol and
                          max_iter ignored; 0: tolerance mode */
   int32_t prec;       /* nn_prec */
-  int32_t flags;      /* 0 or NN_FLAG_TIME_GEMMS; other bits must be 0 */
+  int32_t flags;      /* NN_FLAG_TIME_GEMMS | NN_FLAG_DEVICE_STOP or 0; other
+                         bits must be 0 */
   int32_t power_k;    /* NN_X0_POWER_*: power steps k, 1..NN_POWER_MAX_K (the
                          start then costs k + 1 matrix-vector products with A,
                          twice that for POWER_TRANSPOSE); v_i = 2 u_i - 1 with
@@ -168,7 +181,8 @@ size_t nn_workspace_size(int64_t n, nn_dtype dtype, const nn_params* params);
  *          aligned; its contents are scratch.
  *   info   optional host pointer; filled on return.
  * Tolerance mode blocks until the status is known (one 8-byte read-back per
- * nest).  Fixed mode (params->fixed_iter > 0) blocks once at the end.
+ * nest, or every few nests with NN_FLAG_DEVICE_STOP).  Fixed mode
+ * (params->fixed_iter > 0) blocks once at the end.
  * Supported: F64, F32, C64, C128 plain; F64 mixed. */
 nn_status nn_invert(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx,
                     int64_t n, nn_dtype dtype, const nn_params* params,

@@ -54,6 +54,7 @@ struct PlainWs {
   double* pw = nullptr;       // start-iterate scratch (power steps)
   double* scal = nullptr;     // [0] den
   double* stats = nullptr;    // rms per nest
+  DevCtl* ctl = nullptr;      // device-side stopping rules
   size_t bytes = 0;
 };
 
@@ -72,6 +73,7 @@ PlainWs carve_plain(void* base, int64_t n, nn_dtype dt, int depth) {
   w.pw = static_cast<double*>(c.take(sizeof(double) * start_scratch_doubles(n)));
   w.scal = static_cast<double*>(c.take(sizeof(double) * 8));
   w.stats = static_cast<double*>(c.take(sizeof(double) * kStatSlots));
+  w.ctl = static_cast<DevCtl*>(c.take(sizeof(DevCtl)));
   w.bytes = c.off;
   return w;
 }
@@ -90,7 +92,7 @@ nn_status check_params(const nn_params* p) {
     if (!(p->tol >= 0.0) || p->max_iter < 1) return NN_ERR_ARG;
   }
   if (p->prec != NN_PREC_PLAIN && p->prec != NN_PREC_MIXED) return NN_ERR_ARG;
-  if (p->flags & ~NN_FLAG_TIME_GEMMS) return NN_ERR_ARG;
+  if (p->flags & ~(NN_FLAG_TIME_GEMMS | NN_FLAG_DEVICE_STOP)) return NN_ERR_ARG;
   return NN_OK;
 }
 
@@ -126,9 +128,10 @@ struct Ctl {
     ++gemms;
     return err;
   }
-  float gemm_ms() const {
+  // Summed duration of the first `limit` timed launches (all by default).
+  float gemm_ms(int limit = 1 << 30) const {
     float tot = 0.f;
-    for (int i = 0; i < timed; ++i) {
+    for (int i = 0; i < timed && i < limit; ++i) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ctx->ev_gemm[2 * i], ctx->ev_gemm[2 * i + 1]) == hipSuccess)
         tot += ms;
@@ -164,23 +167,135 @@ hipError_t residual_rms(Ctl& c, Elem e, bool cplx, const GemmPlan& plan, const v
   return launch_rms_reduce(part, plan.num_tiles(), n, rms_out, c.ctx->stream);
 }
 
+// gemms < 0: every launch made did work (c.gemms); else the launches that did
+// work, a prefix of those made (device-side stopping).
 nn_status finish_info(Ctl& c, nn_status st, int iters, double rms, int n_trace,
-                      const double* trace) {
+                      const double* trace, int gemms = -1) {
+  if (gemms < 0) gemms = c.gemms;
   if (c.info) {
     c.info->status = st;
     c.info->iters = iters;
     c.info->rms = rms;
-    c.info->gemms = c.gemms;
+    c.info->gemms = gemms;
     for (int i = 0; i < 3; ++i) c.info->prec_gemms[i] = 0;
-    c.info->prec_gemms[is_double(c.dt) ? 2 : 1] = c.gemms;
+    c.info->prec_gemms[is_double(c.dt) ? 2 : 1] = gemms;
     c.info->n_trace = n_trace;
     for (int i = 0; i < n_trace && i < NN_TRACE_MAX; ++i) c.info->rms_trace[i] = trace[i];
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c.ctx->ev_start, c.ctx->ev_stop) == hipSuccess)
       c.info->device_ms = ms;
-    c.info->gemm_ms = c.gemm_ms();
+    c.info->gemm_ms = c.gemm_ms(gemms);
   }
   return st;
+}
+
+// Nests to enqueue before the host next reads the device control block: the
+// fewest m >= 1 with rms^((d+1)^m) < tol.  A nest maps R to R^(d+1), and for
+// a normal R the power-mean inequality gives rms_{k+1} >= rms_k^(d+1), so
+// every one of these nests is needed; capped at kChunkMax nests (a start far
+// from convergence, or a non-normal residual that falls faster).
+constexpr int kChunkMax = 16;
+int nests_ahead(double rms, double tol, int d) {
+  if (!(rms < 1.0) || !(rms > 0.0) || !(tol > 0.0) || tol >= 1.0) return 1;
+  const double need = log(tol) / log(rms);  // (d+1)^m must exceed this
+  int m = 1;
+  for (double p = d + 1.0; p <= need && m < kChunkMax; p *= d + 1.0) ++m;
+  return m;
+}
+
+// The plain tolerance-mode loop with the stopping rules on the device
+// (NN_FLAG_DEVICE_STOP).  After the residual of nest index k, one kernel
+// reduces its rms and applies the rules; once they fire it sets ctl->done and
+// every product enqueued after it returns at once, so X_k (X_{k-1} for
+// STAGNATED) is left where the ping-pong put it: X_j is in the caller's X for
+// even j and in the workspace's xalt for odd j.  The host enqueues
+// nests_ahead() nests per read of the control block.
+nn_status run_plain_device_stop(Ctl& c, const void* A, int64_t lda, void* X, int64_t ldx,
+                                const PlainWs& w) {
+  nn_ctx* ctx = c.ctx;
+  const nn_params* prm = c.prm;
+  const int64_t n = c.n;
+  const nn_dtype dt = c.dt;
+  hipStream_t s = ctx->stream;
+  const bool cplx = is_complex(dt);
+  const Elem e = is_double(dt) ? Elem::F64 : Elem::F32;
+  const int cm = cplx ? 2 : 1;
+  const int64_t nr = cm * n;
+  const GemmPlan plan = plan_gemm(e, n, nr);
+  const size_t esz = elem_size(dt);
+  const int d = prm->depth;
+  const int32_t* skip = &w.ctl->done;
+
+  if (prm->x0 != NN_X0_GIVEN)
+    HIP_TRY(launch_start(dt, prm->x0, prm->power_k, A, lda, X, ldx, n, w.denpart, w.pw, w.scal,
+                         s));
+  HIP_TRY(launch_ctl_init(w.ctl, prm->x0 != NN_X0_GIVEN ? w.scal : nullptr, s));
+
+  void* buf[2] = {X, w.xalt};
+  const int64_t ld[2] = {ldx, n};
+  // residual of nest index k (X_k in buf[k & 1]) and the rules for k
+  auto residual = [&](int k) -> hipError_t {
+    const int b = k & 1;
+    GemmArgs g{A, lda * cm, buf[b], ld[b] * cm, w.r, nr, nullptr, 0, n, nr, nr, -1.0, 1.0, w.part};
+    g.skip = skip;
+    hipError_t err = c.gemm(e, cplx, plan, g);
+    if (err != hipSuccess) return err;
+    return launch_rms_control(w.part, plan.num_tiles(), n, w.stats + std::min(k, kStatSlots - 1),
+                              w.ctl, k, prm->tol, prm->max_iter, s);
+  };
+  // nest k: X_{k+1} = X_k + X_k U_d from R_k
+  auto nest = [&](int k) -> hipError_t {
+    const void* U = w.r;
+    for (int m = 1; m < d; ++m) {
+      void* Un = (m & 1) ? w.u0 : w.u1;
+      GemmArgs g{w.r, nr, U, nr, Un, nr, w.r, nr, n, nr, nr, 1.0, 0.0, nullptr};
+      g.skip = skip;
+      hipError_t err = c.gemm(e, cplx, plan, g);
+      if (err != hipSuccess) return err;
+      U = Un;
+    }
+    const int b = k & 1;
+    GemmArgs g{buf[b], ld[b] * cm, U, nr, buf[b ^ 1], ld[b ^ 1] * cm, buf[b], ld[b] * cm, n, nr,
+               nr, 1.0, 0.0, nullptr};
+    g.skip = skip;
+    return c.gemm(e, cplx, plan, g);
+  };
+
+  HIP_TRY(residual(0));
+  int k = 0;  // residuals enqueued for k = 0..this
+  DevCtl hc;
+  for (;;) {
+    HIP_TRY(hipMemcpyAsync(ctx->host + 1, w.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->host + 6, w.stats + std::min(k, kStatSlots - 1), sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    memcpy(&hc, ctx->host + 1, sizeof(DevCtl));
+    if (hc.done) break;
+    // the rules let every residual up to k pass, so k < max_iter
+    const int m = std::min(nests_ahead(ctx->host[6], prm->tol, d), prm->max_iter - k);
+    for (int j = 0; j < m; ++j, ++k) {
+      HIP_TRY(nest(k));
+      HIP_TRY(residual(k + 1));
+    }
+  }
+
+  const nn_status st = static_cast<nn_status>(hc.status);
+  // products that did work: residuals 0..last_k and the nests between them
+  const int gemms = hc.last_k < 0 ? 0 : hc.last_k * (d + 1) + 1;
+  double trace[NN_TRACE_MAX];
+  const int n_trace = std::min(hc.last_k + 1, NN_TRACE_MAX);
+  if (n_trace > 0)
+    HIP_TRY(hipMemcpyAsync(ctx->host + 8, w.stats, sizeof(double) * n_trace,
+                           hipMemcpyDeviceToHost, s));
+  // the returned iterate to X (for a negative status, the last one, as the
+  // host loop leaves it)
+  if (hc.iters & 1)
+    HIP_TRY(hipMemcpy2DAsync(X, (size_t)ldx * esz, w.xalt, (size_t)n * esz, (size_t)n * esz,
+                             (size_t)n, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipEventRecord(ctx->ev_stop, s));
+  HIP_TRY(hipEventSynchronize(ctx->ev_stop));
+  for (int i = 0; i < n_trace; ++i) trace[i] = ctx->host[8 + i];
+  return finish_info(c, st, hc.iters, hc.rms_ret, n_trace, trace, gemms);
 }
 
 // The plain NN loop: every GEMM in the dtype of A.
@@ -199,6 +314,8 @@ nn_status run_plain(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ld
   int n_trace = 0;
 
   HIP_TRY(hipEventRecord(ctx->ev_start, s));
+  if (prm->fixed_iter == 0 && (prm->flags & NN_FLAG_DEVICE_STOP))
+    return run_plain_device_stop(c, A, lda, X, ldx, w);
   // Start iterate X_0 in the caller's X.
   if (prm->x0 != NN_X0_GIVEN) {
     HIP_TRY(launch_start(dt, prm->x0, prm->power_k, A, lda, X, ldx, n, w.denpart, w.pw, w.scal,

@@ -165,6 +165,66 @@ __global__ void __launch_bounds__(256) rms_reduce_kernel(const double* part, int
   if (threadIdx.x == 0) out[0] = sqrt(red[0] * inv_rows);
 }
 
+// The rms of one residual as rms_reduce_kernel computes it (same order, same
+// bits), then the stopping rules of the tolerance mode for nest index k, in
+// the host loop's order; a set `done` makes the whole kernel a no-op.
+__global__ void __launch_bounds__(256) rms_control_kernel(const double* part, int count,
+                                                          double inv_rows, double* out,
+                                                          DevCtl* ctl, int k, double tol,
+                                                          int max_iter, double sqrtn) {
+  if (ctl->done) return;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double rms = sqrt(red[0] * inv_rows);
+  out[0] = rms;
+  const double prev = ctl->rms_prev;
+  int st = -100;  // no rule fired
+  int iters = k;
+  double ret = rms;
+  if (!isfinite(rms)) st = NN_ERR_NONFINITE;
+  else if (rms < tol) st = NN_OK;
+  else if (k > 0 && rms >= 1.0 && rms > prev) st = NN_ERR_DIVERGED;
+  else if (k > 0 && sqrtn * prev < 0.1 && rms >= prev) {
+    st = NN_STAGNATED;
+    iters = k - 1;
+    ret = prev;
+  } else if (k == max_iter) st = NN_NOT_CONVERGED;
+  ctl->last_k = k;
+  if (st == -100) {
+    ctl->rms_prev = rms;
+    return;
+  }
+  ctl->status = st;
+  ctl->iters = iters;
+  ctl->rms_ret = ret;
+  ctl->done = 1;
+}
+
+// den (may be null): the start scale; not finite -> NONFINITE, <= 0 ->
+// DIVERGED before any nest, as the host loop tests it.
+__global__ void ctl_init_kernel(DevCtl* ctl, const double* den) {
+  int st = NN_OK, done = 0;
+  if (den) {
+    const double v = den[0];
+    if (!isfinite(v)) st = NN_ERR_NONFINITE, done = 1;
+    else if (v <= 0.0) st = NN_ERR_DIVERGED, done = 1;
+  }
+  ctl->done = done;
+  ctl->status = st;
+  ctl->iters = 0;
+  ctl->last_k = -1;
+  ctl->rms_prev = __builtin_nan("");
+  ctl->rms_ret = __builtin_nan("");
+}
+
 constexpr int kSumsqBlocks = 256;
 template <typename T>
 __global__ void __launch_bounds__(256) sumsq_kernel(const T* src, int64_t ld, int64_t rows,
@@ -335,6 +395,18 @@ hipError_t launch_rms_reduce(const double* partials, int count, int64_t n_rows, 
                              hipStream_t s) {
   hipLaunchKernelGGL(rms_reduce_kernel, dim3(1), dim3(256), 0, s, partials, count,
                      1.0 / (double)n_rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_init(DevCtl* ctl, const double* den, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, ctl, den);
+  return hipGetLastError();
+}
+
+hipError_t launch_rms_control(const double* partials, int count, int64_t n_rows, double* out,
+                              DevCtl* ctl, int k, double tol, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(rms_control_kernel, dim3(1), dim3(256), 0, s, partials, count,
+                     1.0 / (double)n_rows, out, ctl, k, tol, max_iter, sqrt((double)n_rows));
   return hipGetLastError();
 }
 

@@ -123,6 +123,7 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC, int VEC, 
           bool EXACT>
 __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(OCC)))
     gemm_kernel(GemmArgs p, int tiles_m, int tiles_n) {
+  if (p.skip && *p.skip) return;  // uniform: the whole workgroup leaves
   constexpr int NT = WM * WN * 64;
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
@@ -371,6 +372,7 @@ constexpr int kSplitChunks = 8;
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) splitk_epilogue(GemmArgs p, int split, int bm, int bn,
                                                        int tiles_n, double* ssbuf) {
+  if (p.skip && *p.skip) return;
   __shared__ double red[256];
   const int tile = blockIdx.x / kSplitChunks, band = blockIdx.x % kSplitChunks;
   const int rows = bm / kSplitChunks;

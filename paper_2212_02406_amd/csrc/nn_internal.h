@@ -31,6 +31,10 @@ struct GemmArgs {
   // gemm_work_bytes() for the split partial products; null runs unsplit.
   void* work = nullptr;
   int64_t kchunk = 0;  // set by launch_gemm: k extent of one split (0: all of K)
+  // Device flag (may be null): when *skip is nonzero at launch the kernel
+  // returns at once without touching C or the partials (a loop whose stopping
+  // rules run on the device enqueues nests past its stop as no-ops).
+  const int32_t* skip = nullptr;
 };
 
 enum class Elem { F64, F32, BF16IN_F32OUT };
@@ -128,6 +132,28 @@ hipError_t launch_norm_reduce(const double* part, int64_t count, double mult, do
 // Sum `count` FP64 partials in a fixed order; out[0] <- sqrt(sum / n_rows).
 hipError_t launch_rms_reduce(const double* partials, int count, int64_t n_rows, double* out,
                              hipStream_t s);
+
+// Control block of a tolerance-mode loop whose stopping rules run on the
+// device.  `done` is the skip flag of the loop's GEMMs; when it is set,
+// status/iters/rms_ret hold the outcome, with the meanings of the host loop.
+struct DevCtl {
+  int32_t done;
+  int32_t status;
+  int32_t iters;
+  int32_t last_k;   // index of the last residual the rules were applied to
+  double rms_prev;  // rms of the previous residual that passed every rule
+  double rms_ret;   // rms of the returned iterate
+};
+// ctl <- {done 0, status OK, iters 0, last_k -1, NaN, NaN} (a kernel, not a
+// memset, so the loop can be captured).  With den non-null, the start scale
+// den[0] is tested first: not finite -> done with NONFINITE, <= 0 -> done
+// with DIVERGED.
+hipError_t launch_ctl_init(DevCtl* ctl, const double* den, hipStream_t s);
+// Unless ctl->done: out[0] <- rms of nest k's residual (the same fixed-order
+// sum as launch_rms_reduce, so the same bits), then the rules of the host
+// loop for index k with tol and max_iter (stagnation test with sqrt(n_rows)).
+hipError_t launch_rms_control(const double* partials, int count, int64_t n_rows, double* out,
+                              DevCtl* ctl, int k, double tol, int max_iter, hipStream_t s);
 
 // Element-wise copies/casts of an n x n (real extents rows x cols) matrix.
 hipError_t launch_copy(size_t elem_bytes, const void* src, int64_t lds, void* dst, int64_t ldd,

@@ -21,6 +21,11 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "nn.h")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_02406_amd.build`")
 
+# torch first: its HIP runtime is then the one libnn.so binds to, so both
+# share one runtime instance (streams, device memory).  Loading libnn.so
+# first brings in a second runtime, and nn_create then fails on the device.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 # ---- enums (values from include/nn.h) --------------------------------------
@@ -35,6 +40,7 @@ NN_PREC_PLAIN, NN_PREC_MIXED = 0, 1
 NN_MAX_DEPTH = 8
 NN_TRACE_MAX = 128
 NN_FLAG_TIME_GEMMS = 1
+NN_FLAG_DEVICE_STOP = 2
 NN_CNS_MAX_TERMS = 1000000
 NN_SPARSE_MAX_TERMS = 100000000
 
