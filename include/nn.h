@@ -188,6 +188,31 @@ nn_status nn_invert(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ld
                     int64_t n, nn_dtype dtype, const nn_params* params,
                     void* ws, size_t ws_bytes, nn_info* info);
 
+/* Size of the device scratch array behind nn_invert_noalloc (32 MiB). */
+#define NN_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* nn_invert without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (or may not call hipMalloc at
+ * all: allocation-free serving loops, harnesses that forbid it).  The
+ * workspace is a file-scope device array of NN_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends; nn_create
+ * looks up its address on the context's device.  The call makes no
+ * hipMalloc, hipFree or other allocating call.
+ *   Arguments, results and status codes as for nn_invert, plus:
+ *   NN_ERR_WORKSPACE  nn_workspace_size(n, dtype, params) exceeds
+ *                     NN_NOALLOC_SCRATCH_BYTES (plain FP64 / complex64 up to
+ *                     n = 1441, 1178, 1021 at depths 1, 2, 3; FP32 up to
+ *                     2031, 1662, 1441; complex128 up to 1021, 834, 722;
+ *                     mixed FP64 at depth 2 up to 700); nothing is launched
+ *                     and X is untouched.
+ *   NN_ERR_ARG        also for params->flags with NN_FLAG_TIME_GEMMS.
+ * Every call on one device shares that device's array and leaves its contents
+ * behind (the call needs no part of it cleared).  Calls that overlap on one
+ * device, from any context or stream, race on it: the caller must order them
+ * (one stream, or events between streams). */
+nn_status nn_invert_noalloc(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx,
+                            int64_t n, nn_dtype dtype, const nn_params* params, nn_info* info);
+
 /* Workspace bytes nn_solve needs. */
 size_t nn_solve_workspace_size(int64_t n, int64_t nrhs, nn_dtype dtype,
                                const nn_params* params);

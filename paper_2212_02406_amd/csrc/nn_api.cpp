@@ -19,12 +19,39 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "nn_internal.h"
 
 namespace nn {
 namespace {
+
+// Workspace of nn_invert_noalloc: a file-scope device array.  Every device
+// the library runs on holds its own copy until the process ends.  In host
+// code `scratch` names a host-side stand-in, not the device memory: its
+// device address comes from hipGetSymbolAddress (scratch_address), once per
+// device, with that device current, and only that address is ever used.
+static __device__ __align__(256) unsigned char scratch[NN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (current on entry).
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kHostSlots = NN_TRACE_MAX + 16;
@@ -456,6 +483,10 @@ nn_status nn_create(nn_ctx** out, int device, void* stream) {
     c->arch[i] = 0;
   }
   if (!c->arch[0]) strcpy(c->arch, "unknown");
+  if (scratch_address(device, &c->scratch) != hipSuccess) {
+    nn_destroy(c);
+    return NN_ERR_HIP;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * kHostSlots,
                     hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess) {
@@ -512,6 +543,19 @@ nn_status nn_invert(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ld
   if (hipSetDevice(ctx->device) != hipSuccess) return NN_ERR_HIP;
   const PlainWs w = carve_plain(ws, n, dt, prm->depth);
   return run_plain(ctx, A, lda, X, ldx, n, dt, prm, w, info);
+}
+
+nn_status nn_invert_noalloc(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ldx,
+                            int64_t n, nn_dtype dt, const nn_params* prm, nn_info* info) {
+  nn_status v = validate_invert(ctx, A, lda, X, ldx, n, dt, prm);
+  if (v != NN_OK) return v;
+  // event timing would create events on first use
+  if (prm->flags & NN_FLAG_TIME_GEMMS) return NN_ERR_ARG;
+  if (!ctx->scratch) return NN_ERR_HIP;
+  const size_t need = nn_workspace_size(n, dt, prm);
+  if (need == 0) return prm->prec == NN_PREC_MIXED ? NN_ERR_UNSUPPORTED : NN_ERR_ARG;
+  if (need > (size_t)NN_NOALLOC_SCRATCH_BYTES) return NN_ERR_WORKSPACE;
+  return nn_invert(ctx, A, lda, X, ldx, n, dt, prm, ctx->scratch, NN_NOALLOC_SCRATCH_BYTES, info);
 }
 
 size_t nn_solve_workspace_size(int64_t n, int64_t nrhs, nn_dtype dt, const nn_params* prm) {

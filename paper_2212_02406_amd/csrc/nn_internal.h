@@ -270,4 +270,5 @@ struct nn_ctx {
   hipEvent_t* ev_gemm = nullptr;  // 2 * kTimedGemms events, created on first timed call
   nn::BatchedTune tune[kTuneSlots];
   nn::BatchedGraph bgraph;
+  void* scratch = nullptr;  // device address of this device's static scratch array
 };

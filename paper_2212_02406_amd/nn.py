@@ -41,6 +41,7 @@ NN_MAX_DEPTH = 8
 NN_TRACE_MAX = 128
 NN_FLAG_TIME_GEMMS = 1
 NN_FLAG_DEVICE_STOP = 2
+NN_NOALLOC_SCRATCH_BYTES = 32 << 20
 NN_CNS_MAX_TERMS = 1000000
 NN_SPARSE_MAX_TERMS = 100000000
 
@@ -119,6 +120,8 @@ _SIGS = {
     "nn_workspace_size": (_sz, [_i64, ctypes.c_int, _PP]),
     "nn_invert": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _i64, ctypes.c_int, _PP, _p, _sz,
                                  ctypes.POINTER(nn_info)]),
+    "nn_invert_noalloc": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _i64, ctypes.c_int, _PP,
+                                         ctypes.POINTER(nn_info)]),
     "nn_solve_workspace_size": (_sz, [_i64, _i64, ctypes.c_int, _PP]),
     "nn_solve": (ctypes.c_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i64, _i64, ctypes.c_int, _PP,
                                 _p, _sz, ctypes.POINTER(nn_info), ctypes.POINTER(ctypes.c_double)]),
@@ -300,6 +303,25 @@ def invert(A, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0, pr
     if check and st < 0 and st not in (NN_ERR_DIVERGED, NN_ERR_NONFINITE):
         raise NNError(st, "nn_invert")
     return X, d
+
+
+def invert_noalloc(A, X, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0,
+                   prec="plain", ctx: Context | None = None, flags=0, power_k=8):
+    """nn_invert_noalloc: X ~ A^-1 with the library's static device scratch
+    (no workspace, no allocation; X must be given).  Returns (status, info)."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("A must be a square row-major matrix")
+    if X.shape != A.shape or X.dtype != A.dtype or X.stride(1) != 1:
+        raise ValueError("X must be a row-major matrix of A's shape and dtype")
+    prm = make_params(depth, x0, tol, max_iter, fixed_iter, prec, flags, power_k)
+    ctx = ctx or default_context(A.device.index or 0)
+    info = nn_info()
+    st = nn_invert_noalloc(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.stride(0),
+                           ctypes.c_void_p(X.data_ptr()), X.stride(0), A.shape[0],
+                           dtype_code(A), ctypes.byref(prm), ctypes.byref(info))
+    d = info.as_dict()
+    d["status"] = st
+    return st, d
 
 
 def solve(A, B, depth=2, x0="transpose", tol=1e-12, max_iter=100, fixed_iter=0,

@@ -109,6 +109,28 @@ def test_argument_errors_before_launch():
     assert nn.nn_workspace_size(16, nn.NN_F64, ctypes.byref(bad)) == 0
     assert nn.nn_workspace_size(0, nn.NN_F64, ctypes.byref(p)) == 0
     assert nn.nn_workspace_size(16, 9, ctypes.byref(p)) == 0
+    bad = nn.make_params(flags=4)
+    assert nn.nn_workspace_size(16, nn.NN_F64, ctypes.byref(bad)) == 0
+    assert nn.nn_invert_noalloc(None, fake, 4, fake, 4, 4, nn.NN_F64, ctypes.byref(p),
+                                ctypes.byref(info)) == nn.NN_ERR_ARG
+
+
+def test_noalloc_scratch_limits():
+    """The largest sizes whose workspace fits nn_invert_noalloc's static
+    scratch, as include/nn.h states them."""
+    nn = _nn()
+    L = nn.NN_NOALLOC_SCRATCH_BYTES
+    assert L == 32 << 20
+    stated = {nn.NN_F64: (1441, 1178, 1021), nn.NN_C64: (1441, 1178, 1021),
+              nn.NN_F32: (2031, 1662, 1441), nn.NN_C128: (1021, 834, 722)}
+    for dt, ns in stated.items():
+        for d, n in zip((1, 2, 3), ns):
+            p = nn.make_params(depth=d)
+            assert 0 < nn.nn_workspace_size(n, dt, ctypes.byref(p)) <= L
+            assert nn.nn_workspace_size(n + 1, dt, ctypes.byref(p)) > L
+    p = nn.make_params(depth=2, prec="mixed", x0="identity")
+    assert 0 < nn.nn_workspace_size(700, nn.NN_F64, ctypes.byref(p)) <= L
+    assert nn.nn_workspace_size(701, nn.NN_F64, ctypes.byref(p)) > L
 
 
 def test_cns_argument_errors_and_workspace():
