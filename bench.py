@@ -63,8 +63,13 @@ def parse():
     ap.add_argument("--legs", default="small,fp32,factorized,cns,starts,sparse,batched,mixed,serving",
                     help="comma list of extra workloads to run")
     ap.add_argument("--mixed-n", type=int, default=16384)
-    ap.add_argument("--serve-pool", type=int, default=64)
-    ap.add_argument("--serve-requests", type=int, default=192)
+    ap.add_argument("--serve-pool", type=int, default=1024)
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests of the closed-loop capacity runs")
+    ap.add_argument("--serve-window", type=float, default=30.0,
+                    help="seconds of each sustained Poisson stream")
+    ap.add_argument("--serve-overload", type=float, default=5.0,
+                    help="seconds of the 2000 req/s overload window")
     ap.add_argument("--host-input", action="store_true",
                     help="build the headline and mixed-leg matrices with host (NumPy) QR only, no GPU library "
                          "kernels before the NN launches (for counter collection)")
@@ -523,39 +528,50 @@ def leg_sparse(nn, torch, workloads, np, grid=2048, nrhs=16, shift=0.5):
     return out
 
 
-def leg_serving(nn, torch, workloads, np, pool_size, n_req):
-    """Poisson request stream over a pool of FP32 SPD / complex64 HPD
-    matrices, N log-uniform in [32, 4096], cond log-uniform in [10, 1e4],
-    tol 1e-4 or 1e-8: closed-loop capacity, open loop at 2000 req/s and at
-    half the capacity, and the same requests run one by one through plain
-    FP64 nn_invert."""
+def leg_serving(nn, torch, workloads, np, pool_size, n_req, window_s=30.0, overload_s=5.0):
+    """The serving workload over a pool of FP32 SPD / complex64 HPD matrices,
+    N log-uniform in [32, 4096], cond log-uniform in [10, 1e4], tol 1e-4 or
+    1e-8: closed-loop capacity on n_req requests; sustained Poisson streams
+    of window_s seconds at 0.5 and 0.9 of that capacity (every arrival served
+    to the end); a bounded overload window of overload_s seconds at the
+    2000 req/s of the workload's definition (queue length over time, the rate
+    served; unfinished requests are dropped at the window's end); and the
+    capacity requests one by one through plain FP64 nn_invert.  Requests are
+    drawn uniformly from the pool; latency is arrival to result in host
+    memory."""
+    t_build = time.perf_counter()
     pool = workloads.serving_pool(pool_size, seed=5)
     mats = []
     for e in pool:
         mats.append(torch.from_numpy(workloads.build_request(
             e, device="cuda" if e["n"] >= 512 else None)).cuda())
     torch.cuda.synchronize()
+    log(f"serving pool of {pool_size} built in {time.perf_counter() - t_build:.1f} s")
     g = workloads.rng(55)
-    picks = g.integers(0, pool_size, n_req)
-    tols = [pool[i]["tol"] for i in picks]
     d = 2
 
-    def flop_of(rec):
-        f = (rec["iters"] * (d + 1) + 1) * 2.0 * rec["n"] ** 3
-        return f * (4 if pool[picks[rec["id"]]]["complex"] else 1)
+    def flop_of(entry, iters):
+        f = (iters * (d + 1) + 1) * 2.0 * entry["n"] ** 3
+        return f * (4 if entry["complex"] else 1)
 
-    def run(rate, x0="power_identity"):
+    def run(arrivals, picks, x0="power_identity", stop_s=None):
+        """Serve requests i = 0.. arriving at arrivals[i] (seconds) with pool
+        entry picks[i].  stop_s: stop at that time (overload), else drain."""
+        n_req = len(picks)
         srv = nn.Server(96 << 30, depth=d, x0=x0, max_active=512, n_streams=4)
         srv.submit(-1, mats[0], 1e-4)
         srv.run_until_idle()
         srv.release(-1)
-        arr = np.zeros(n_req) if rate is None else np.cumsum(g.exponential(1.0 / rate, n_req))
         t0 = time.perf_counter()
-        nxt, lat, recs = 0, {}, []
+        nxt, lat, recs, queue = 0, {}, [], []
+        next_sample = 0.0
         while len(lat) < n_req:
             now = time.perf_counter() - t0
-            while nxt < n_req and arr[nxt] <= now:
-                srv.submit(nxt, mats[picks[nxt]], tols[nxt], 100)
+            if stop_s is not None and now >= stop_s:
+                break
+            while nxt < n_req and arrivals[nxt] <= now:
+                e = pool[picks[nxt]]
+                srv.submit(nxt, mats[picks[nxt]], e["tol"], 100)
                 nxt += 1
             s = srv.tick()
             for r in srv.poll():
@@ -563,40 +579,69 @@ def leg_serving(nn, torch, workloads, np, pool_size, n_req):
                     srv.fetch(r["id"], r["n"], r["out_dtype"], out_device="cpu")
                 else:
                     srv.release(r["id"])
-                lat[r["id"]] = time.perf_counter() - t0 - arr[r["id"]]
+                lat[r["id"]] = time.perf_counter() - t0 - arrivals[r["id"]]
                 recs.append(r)
+            now = time.perf_counter() - t0
+            if now >= next_sample:
+                queue.append([round(now, 2), int(s.queued), int(s.active), len(lat), nxt])
+                next_sample += 1.0 if stop_s is None else 0.5
             if s.active == 0 and s.queued == 0 and nxt < n_req:
-                time.sleep(max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 1e-3)))
+                time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 1e-3)))
         wall = time.perf_counter() - t0
         srv.close()
-        L = np.array([lat[i] for i in range(n_req)])
+        L = np.array(list(lat.values())) if lat else np.zeros(1)
         ok = sum(1 for r in recs if r["status"] == 0)
-        return {"offered_req_per_s": rate, "requests": n_req, "wall_s": wall,
-                "inverses_per_s": n_req / wall, "p50_ms": 1e3 * float(np.percentile(L, 50)),
+        return {"requests_arrived": nxt, "requests_done": len(lat), "wall_s": wall,
+                "inverses_per_s": len(lat) / wall,
+                "p50_ms": 1e3 * float(np.percentile(L, 50)),
                 "p99_ms": 1e3 * float(np.percentile(L, 99)),
-                "tflops": sum(flop_of(r) for r in recs) / wall / 1e12,
+                "tflops": sum(flop_of(pool[picks[r["id"]]], r["iters"]) for r in recs) / wall / 1e12,
                 "ok": ok, "promoted_to_fp64": sum(1 for r in recs if r["wide_iters"] > 0),
-                "max_rms_over_tol_ok": max([r["rms"] / tols[r["id"]] for r in recs
-                                            if r["status"] == 0], default=None)}
+                "max_rms_over_tol_ok": max([r["rms"] / pool[picks[r["id"]]]["tol"] for r in recs
+                                            if r["status"] == 0], default=None),
+                "queue_over_time_s_queued_active_done_arrived": queue}
 
-    out = {"capacity_closed_loop": run(None)}
-    log(f"serving capacity: {out['capacity_closed_loop']}")
-    out["capacity_identity_start"] = run(None, "identity")
-    log(f"serving capacity, I / Tr A start: {out['capacity_identity_start']}")
-    out["open_loop_2000"] = run(2000.0)
-    log(f"serving 2000 req/s: {out['open_loop_2000']}")
-    half = 0.5 * out["capacity_closed_loop"]["inverses_per_s"]
-    out["open_loop_half_capacity"] = run(half)
-    log(f"serving {half:.0f} req/s: {out['open_loop_half_capacity']}")
-    # the same requests one by one through plain FP64 nn_invert, same start
+    out = {}
+    cap_picks = g.integers(0, pool_size, n_req)
+    out["capacity_closed_loop"] = run(np.zeros(n_req), cap_picks)
+    cap = out["capacity_closed_loop"]["inverses_per_s"]
+    log(f"serving capacity: {cap:.1f} inverses/s")
+    out["capacity_identity_start"] = run(np.zeros(n_req), cap_picks, "identity")
+    log(f"serving capacity, I / Tr A start: "
+        f"{out['capacity_identity_start']['inverses_per_s']:.1f} inverses/s")
+    for frac in (0.5, 0.9):
+        rate = frac * cap
+        m = int(rate * window_s * 1.5) + 16
+        arr = np.cumsum(g.exponential(1.0 / rate, m))
+        arr = arr[arr < window_s]
+        picks = g.integers(0, pool_size, arr.size)
+        rec = run(arr, picks)
+        rec.update(offered_req_per_s=rate, window_s=window_s, frac_of_capacity=frac)
+        out[f"stream_{frac:g}x_capacity"] = rec
+        log(f"serving stream {frac:g}x capacity ({rate:.1f} req/s, {arr.size} requests over "
+            f"{window_s:g} s): p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms, "
+            f"{rec['inverses_per_s']:.1f} inverses/s")
+    rate = 2000.0
+    arr = np.cumsum(g.exponential(1.0 / rate, int(rate * overload_s * 1.5)))
+    arr = arr[arr < overload_s]
+    picks = g.integers(0, pool_size, arr.size)
+    rec = run(arr, picks, stop_s=overload_s)
+    rec.update(offered_req_per_s=rate, window_s=overload_s,
+               note=("overload: the offered rate exceeds capacity; the window stops at "
+                     f"{overload_s:g} s and unfinished requests are dropped, so p50/p99 cover "
+                     "only the requests that finished inside it"))
+    out["overload_2000_req_per_s"] = rec
+    log(f"serving overload 2000 req/s: {rec['requests_arrived']} arrived, "
+        f"{rec['requests_done']} done in {overload_s:g} s")
+    # the capacity requests one by one through plain FP64 nn_invert, same start
     wide = {}
-    for i in set(int(x) for x in picks):
+    for i in set(int(x) for x in cap_picks):
         wide[i] = mats[i].to(torch.complex128 if mats[i].is_complex() else torch.float64)
     for x0 in ("power_identity", "identity"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for r, i in enumerate(picks):
-            nn.invert(wide[int(i)], depth=d, x0=x0, tol=tols[r], max_iter=100)
+        for i in cap_picks:
+            nn.invert(wide[int(i)], depth=d, x0=x0, tol=pool[int(i)]["tol"], max_iter=100)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         key = "plain_fp64_sequential" + ("" if x0 == "power_identity" else "_identity_start")
@@ -604,10 +649,12 @@ def leg_serving(nn, torch, workloads, np, pool_size, n_req):
         log(f"serving {key}: {out[key]}")
     out["served_vs_plain_fp64"] = (out["capacity_closed_loop"]["inverses_per_s"] /
                                    out["plain_fp64_sequential"]["inverses_per_s"])
-    out["workload"] = (f"{n_req} requests drawn from a pool of {pool_size} (seed 5): FP32 SPD or "
-                       "complex64 HPD 50/50, N log-uniform [32,4096], cond log-uniform [10,1e4], "
-                       "tol 1e-4 or 1e-8 50/50; depth 2, Theta_2(8) I start (I / Tr A for the "
-                       "*_identity_start entries); latency = arrival to result in host memory")
+    out["workload"] = (f"pool of {pool_size} (seed 5): FP32 SPD or complex64 HPD 50/50, N "
+                       "log-uniform [32,4096], cond log-uniform [10,1e4], tol 1e-4 or 1e-8 50/50; "
+                       f"capacity on {n_req} requests; Poisson streams of {window_s:g} s at 0.5x "
+                       f"and 0.9x capacity; {overload_s:g} s at 2000 req/s; depth 2, "
+                       "Theta_2(8) I start (I / Tr A for the *_identity_start entries); latency "
+                       "= arrival to result in host memory")
     return out
 
 
@@ -714,7 +761,8 @@ def main():
         torch.cuda.empty_cache()
     if "serving" in legs:
         extra["serving"] = leg_serving(nn, torch, workloads, np, args.serve_pool,
-                                       args.serve_requests)
+                                       args.serve_requests, args.serve_window,
+                                       args.serve_overload)
     out["extra"] = extra
 
     if not args.no_cpu:

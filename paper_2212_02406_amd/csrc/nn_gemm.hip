@@ -362,6 +362,123 @@ __global__ void __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_e
   }
 }
 
+// Small products (n up to a few hundred), where 32x32 tiles leave most of the
+// 256 CUs idle and a single wave per tile waits out every load: one 16x16
+// output tile per workgroup, its k range dealt to four waves in chunks of 64
+// (chunk c to wave c mod 4).  A chunk needs no LDS staging: at MFMA step j
+// lane (r, q) = (lane % 16, lane / 16) supplies A[m0+r][k0+16q+j] and
+// B[k0+16q+j][n0+r], so a lane's 16 A operands are one contiguous row run
+// (vector loads) and the 16 lanes of a B load read one contiguous row run.
+// The four waves' accumulators are summed through LDS in wave order by wave
+// 0, which applies the epilogue and writes the tile's sum of squares.
+// EXACT: M, N multiples of 16, K of 64, A rows 16-byte aligned (no checks).
+constexpr int kSmallChunk = 64;
+
+template <typename T, bool CPLX, bool EXACT>
+__global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m, int tiles_n) {
+  if (p.skip && *p.skip) return;
+  using acc_t = typename Mfma<T>::acc_t;
+  constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  __shared__ acc_t red[3][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  int pm, pn;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  grouped_tile(bid, tiles_m, tiles_n, pm, pn);
+  const int64_t m0 = (int64_t)pm * 16, n0 = (int64_t)pn * 16;
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const T* __restrict__ A = static_cast<const T*>(p.A);
+  const T* __restrict__ B = static_cast<const T*>(p.B);
+  const int64_t arow = m0 + lr, bcol = n0 + lr;
+  const bool arow_ok = EXACT || arow < M, bcol_ok = EXACT || bcol < N;
+
+  acc_t acc = acc_t{};
+  const int64_t nchunks = (K + kSmallChunk - 1) / kSmallChunk;
+  for (int64_t c = wave; c < nchunks; c += 4) {
+    const int64_t kb = c * kSmallChunk + 16 * lq;  // this lane's first k
+    T a[16], b[16];
+    if constexpr (EXACT) {
+      const vec_t* ap = reinterpret_cast<const vec_t*>(A + arow * p.lda + kb);
+#pragma unroll
+      for (int v = 0; v < 16 / V; ++v) {
+        const vec_t x = ap[v];
+#pragma unroll
+        for (int e = 0; e < V; ++e) a[v * V + e] = x[e];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t k = kb + j;
+        a[j] = (arow_ok && k < K) ? A[arow * p.lda + k] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t k = kb + j;
+      if constexpr (CPLX) {
+        // real form of a complex B: row 2s is row s as stored, row 2s+1 is
+        // row s with (re, im) -> (-im, re)
+        const T* row = B + (k >> 1) * p.ldb;
+        T v = T(0);
+        if (bcol_ok && (EXACT || k < K)) {
+          if (!(k & 1)) v = row[bcol];
+          else v = (bcol & 1) ? row[bcol - 1] : -row[bcol + 1];
+        }
+        b[j] = v;
+      } else {
+        b[j] = (bcol_ok && (EXACT || k < K)) ? B[k * p.ldb + bcol] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc = Mfma<T>::run(a[j], b[j], acc);
+  }
+
+  if (wave > 0) red[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) acc += red[w][lane];
+
+  T* __restrict__ C = static_cast<T*>(p.C);
+  const T* __restrict__ E = static_cast<const T*>(p.E);
+  const T alpha = (T)p.alpha, diag = (T)p.diag;
+  double ss = 0.0;
+  const int64_t c = bcol;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t r = m0 + Mfma<T>::row(lq, t);
+    if (EXACT || (r < M && c < N)) {
+      T v = alpha * acc[t];
+      if (E) v += E[r * p.lde + c];
+      if (CPLX ? (c == 2 * r) : (c == r)) v += diag;
+      C[r * p.ldc + c] = v;
+      ss += (double)v * (double)v;
+    }
+  }
+  if (p.partials) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) p.partials[pm * tiles_n + pn] = ss;
+  }
+}
+
+template <typename T, bool CPLX>
+hipError_t launch_small(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
+  const int ntile = plan.num_tiles();
+  if (ntile <= 0) return hipSuccess;
+  const size_t ab = reinterpret_cast<uintptr_t>(a.A);
+  const bool exact = a.M % 16 == 0 && a.N % 16 == 0 && a.K % kSmallChunk == 0 && ab % 16 == 0 &&
+                     (a.lda * (int64_t)sizeof(T)) % 16 == 0;
+  if (exact)
+    hipLaunchKernelGGL((gemm_small_kernel<T, CPLX, true>), dim3(ntile), dim3(256), 0, s, a,
+                       plan.tiles_m, plan.tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_small_kernel<T, CPLX, false>), dim3(ntile), dim3(256), 0, s, a,
+                       plan.tiles_m, plan.tiles_n);
+  return hipGetLastError();
+}
+
 // Split-K epilogue, kSplitChunks workgroups per output tile (each a band of
 // the tile's rows): C = alpha * sum_s W_s + E + diag * I with the partials
 // summed in split order; each band's sum of squares goes to ssbuf and
@@ -428,6 +545,7 @@ inline TileShape shape_of(Tile t) {
     case Tile::T256K8:
     case Tile::T256: return {256, 128};
     case Tile::T64: return {64, 64};
+    case Tile::T16: return {16, 16};
     case Tile::T32:
     case Tile::kCount: return {32, 32};
   }
@@ -474,6 +592,7 @@ hipError_t launch_one(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
 template <typename T, int VEC, bool CPLX>
 hipError_t launch_tile(const GemmPlan& plan, const GemmArgs& a, hipStream_t s) {
   switch (plan.tile) {
+    case Tile::T16: return launch_small<T, CPLX>(plan, a, s);
     case Tile::T128: return launch_one<T, 128, 128, 16, 2, 2, 1, VEC, CPLX>(plan, a, s);
     case Tile::T128W8: return launch_one<T, 128, 128, 16, 2, 4, 2, VEC, CPLX>(plan, a, s);
     case Tile::T128K8: return launch_one<T, 128, 128, 8, 2, 2, 2, VEC, CPLX>(plan, a, s);
@@ -493,7 +612,8 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 bool tile_override(Tile* t) {
   const char* v = getenv("NN_GEMM_TILE");
   if (!v) return false;
-  const char* names[] = {"T128", "T128W8", "T128K8", "T128W8K8", "T256K8", "T256", "T64", "T32"};
+  const char* names[] = {"T128", "T128W8", "T128K8", "T128W8K8", "T256K8", "T256", "T64", "T32",
+                         "T16"};
   for (int i = 0; i < (int)Tile::kCount; ++i) {
     if (strcmp(v, names[i]) == 0) {
       *t = static_cast<Tile>(i);
@@ -505,6 +625,15 @@ bool tile_override(Tile* t) {
 
 }  // namespace
 
+// Largest output (M x N real elements) for which the small-product kernel
+// beats the 32x32 and 64x64 tiles on gfx950 (square products, ten depth-2
+// nests, microseconds per GEMM): FP64 n = 256: 7.3 against 18.8 (T32);
+// n = 640: 34.4 against 39.1; n = 768: 49.0 against 46.8.  FP32 n = 256: 7.7
+// against 13.5; n = 768: 27.2 against 33.1; n = 1024: 54.4 against 42.4.
+// Longer k extents (thin products over a large n) keep the split tiles.
+constexpr int64_t kSmallArea64 = 640 * 640, kSmallArea32 = 768 * 768;
+constexpr int64_t kSmallMaxK = 1536;
+
 // Tile choice by measured throughput on gfx950 at N = 8192: FP64 runs best
 // with 8 waves of 64x32 and a 16-deep k-slab (71.7 TFLOP/s), FP32 with the
 // 256x128 tile (140.6 TFLOP/s).  Smaller problems drop to smaller tiles while
@@ -515,6 +644,7 @@ GemmPlan plan_gemm(Elem e, int64_t M, int64_t N) {
   if (!tile_override(&p.tile)) {
     if (e == Elem::F32 && tiles(256, 128) >= 256) p.tile = Tile::T256;
     else if (tiles(128, 128) >= 256) p.tile = Tile::T128W8;
+    else if (M * N <= (e == Elem::F64 ? kSmallArea64 : kSmallArea32)) p.tile = Tile::T16;
     else if (tiles(64, 64) >= 128) p.tile = Tile::T64;
     else p.tile = Tile::T32;
   }
@@ -530,6 +660,15 @@ int slab_of(Tile t) {
 
 GemmPlan plan_gemm_k(Elem e, int64_t M, int64_t N, int64_t K) {
   GemmPlan p = plan_gemm(e, M, N);
+  if (p.tile == Tile::T16) {
+    if (K <= kSmallMaxK || getenv("NN_GEMM_TILE")) return p;  // four waves per tile over k
+    // a long k extent: the split tiles
+    auto tiles = [&](int bm, int bn) { return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn)); };
+    p.tile = tiles(64, 64) >= 128 ? Tile::T64 : Tile::T32;
+    const TileShape sh = shape_of(p.tile);
+    p.tiles_m = (int)((M + sh.bm - 1) / sh.bm);
+    p.tiles_n = (int)((N + sh.bn - 1) / sh.bn);
+  }
   const int64_t slabs = (K + slab_of(p.tile) - 1) / slab_of(p.tile);
   const char* v = getenv("NN_GEMM_SPLIT");
   int s = 1;

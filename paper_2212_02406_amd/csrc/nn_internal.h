@@ -48,9 +48,11 @@ enum class Elem { F64, F32, BF16IN_F32OUT };
 //   T256   256x128, 8 waves of 64x64, BK 16
 //   T64     64x64,  4 waves of 32x32, BK 16
 //   T32     32x32,  1 wave  of 32x32, BK 16
+//   T16     16x16,  4 waves each taking every fourth 64-deep k chunk, summed
+//           in LDS (small products; never split)
 // The environment variable NN_GEMM_TILE (one of the names above) forces one
 // configuration for every GEMM, for tuning and for tests.
-enum class Tile { T128, T128W8, T128K8, T128W8K8, T256K8, T256, T64, T32, kCount };
+enum class Tile { T128, T128W8, T128K8, T128W8K8, T256K8, T256, T64, T32, T16, kCount };
 
 struct GemmPlan {
   Tile tile;

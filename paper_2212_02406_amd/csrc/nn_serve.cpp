@@ -47,61 +47,21 @@
 #include <vector>
 
 #include "nn_internal.h"
+#include "nn_sched.h"
 
 namespace nn {
 namespace {
 
-constexpr size_t kAlign = 256;
+using sched::PoolAlloc;
+using sched::RState;
+using sched::single_dtype;
+using sched::widen;
+using sched::up;
+
+constexpr size_t kAlign = sched::kAlign;
 constexpr int kMaxStreams = 8;
 constexpr int kMaxActiveLimit = 65536;
-constexpr int kMaxBypassTicks = 8;
-constexpr int kBypassScan = 64;
 constexpr int kBatchMaxN = 64;  // the batched kernel's largest size
-
-inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// First-fit allocator over [0, size) with coalescing free list.
-class PoolAlloc {
- public:
-  void reset(size_t size) {
-    free_.clear();
-    if (size) free_[0] = size;
-    used_ = 0;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      *off = it->first;
-      const size_t rest = it->second - bytes, start = it->first + bytes;
-      free_.erase(it);
-      if (rest) free_[start] = rest;
-      used_ += bytes;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t used() const { return used_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t used_ = 0;
-};
 
 // Matrices of one precision phase of a request.
 struct PhaseBufs {
@@ -117,61 +77,41 @@ struct Block {
   bool held = false;
 };
 
-enum class State { Queued, Active, Retired };
-
-struct Request {
-  int64_t id = 0;
-  int64_t n = 0;
-  nn_dtype dt = NN_F32;
-  double tol = 0.0;
-  int32_t max_iter = 0;
+// A request: its scheduling state (sched::Req) plus what the device work
+// needs.
+struct Request : sched::Req {
   const void* src = nullptr;
   int64_t src_ld = 0;
-  State state = State::Queued;
-  int bypassed = 0;  // ticks in which later requests were admitted before it
   Block narrow, wide;
-  bool reserve_wide = false;  // wide block reserved at admission
   PhaseBufs ph[2];            // [0] narrow (single precision), [1] wide
-  int cur_ph = 0;
   double* part = nullptr;     // residual GEMM tile partials
   double* denpart = nullptr;  // norm partials of the transpose start
   double* pw = nullptr;       // power-step scratch of the Theta_2 starts
   double* scal = nullptr;     // [0] den
   int slot = -1;
   int stream = 0;
-  bool fresh = false;  // admitted this tick: den not checked yet
-  bool small = false;  // narrow phase in this tick's batched launch
-  int bidx = -1;       // its index in that launch's arrays
-  bool polled = false;   // its record has been handed out by nn_server_poll
-  bool dropped = false;  // fetched or released before it was polled
-  int cur = 0;         // X[cur] is the current iterate
-  int iters = 0, wide_iters = 0, phase_k = 0;
-  double rms_prev = NAN;
-  int32_t status = NN_OK;
-  int result_buf = 0;  // X buffer holding the result
-  double rms = NAN;
+  int bidx = -1;          // index in this tick's batched launch (small path)
+  bool polled = false;    // its record has been handed out by nn_server_poll
+  bool dropped = false;   // fetched or released before it was polled
   double t_submit = 0, t_admit = 0, t_finish = 0;
 };
 
-bool single_dtype(nn_dtype d) { return d == NN_F32 || d == NN_C64; }
-nn_dtype widen(nn_dtype d) { return d == NN_F32 ? NN_F64 : d == NN_C64 ? NN_C128 : d; }
 Elem elem_of(nn_dtype d) { return is_double(d) ? Elem::F64 : Elem::F32; }
 
-size_t mats_per_phase(int depth) { return 4 + (depth >= 2) + (depth >= 3); }
-
-// Bytes of the per-request control region: tile partials (enough for either
-// precision's plan), norm partials, power-step scratch, scalars.
-size_t control_bytes(int64_t n, nn_dtype dt) {
+// The sizes that fix a request's pool block (tile partials enough for either
+// precision's plan).
+sched::ReqSizes sizes_of(int64_t n, nn_dtype dt, int depth) {
   const int cm = is_complex(dt) ? 2 : 1;
   const int t64 = plan_gemm(Elem::F64, n, cm * n).num_tiles();
   const int t32 = plan_gemm(Elem::F32, n, cm * n).num_tiles();
-  return up(sizeof(double) * (size_t)std::max({t64, t32, 1})) +
-         up(sizeof(double) * den_partials_elems(n)) +
-         up(sizeof(double) * start_scratch_doubles(n)) + up(sizeof(double) * 8);
-}
-
-size_t phase_bytes(int64_t n, nn_dtype dt, int depth) {
-  return mats_per_phase(depth) * up((size_t)n * (size_t)n * elem_size(dt));
+  sched::ReqSizes z;
+  z.part = sizeof(double) * (size_t)std::max({t64, t32, 1});
+  z.denpart = sizeof(double) * den_partials_elems(n);
+  z.pw = sizeof(double) * start_scratch_doubles(n);
+  z.narrow_mat = single_dtype(dt) ? (size_t)n * (size_t)n * elem_size(dt) : 0;
+  z.wide_mat = (size_t)n * (size_t)n * elem_size(widen(dt));
+  z.depth = depth;
+  return z;
 }
 
 }  // namespace
@@ -189,7 +129,7 @@ struct nn_server {
   double* slots_dev = nullptr;   // 2 doubles per slot: rms, den
   double* slots_host = nullptr;  // pinned
   std::priority_queue<int, std::vector<int>, std::greater<int>> free_slots;
-  std::deque<Request*> queued;
+  std::deque<sched::Req*> queued;  // Request objects, in arrival order
   std::vector<Request*> active;
   std::unordered_map<int64_t, Request*> by_id;  // queued, active or retired (not fetched)
   std::deque<Request*> unpolled;
@@ -246,23 +186,19 @@ bool small_path(const nn_server* s, int64_t n, nn_dtype dt, int32_t max_iter) {
 }
 
 size_t footprint_of(const nn_server* s, int64_t n, nn_dtype dt, double tol, bool* reserve_wide) {
-  const int d = s->prm.depth;
-  size_t b = control_bytes(n, dt) + phase_bytes(n, dt, d);
   const bool rw = single_dtype(dt) && tol < s->prm.wide_tol;
-  if (rw) b += phase_bytes(n, widen(dt), d);
   if (reserve_wide) *reserve_wide = rw;
-  return up(b);
+  return sched::admission_bytes(sizes_of(n, dt, s->prm.depth), rw);
 }
 
-void carve_phase(char* p, int64_t n, nn_dtype dt, int depth, PhaseBufs* out) {
-  const size_t m = up((size_t)n * (size_t)n * elem_size(dt));
+void set_phase(char* base, const sched::PhaseLayout& L, nn_dtype dt, PhaseBufs* out) {
   out->dt = dt;
-  out->A = p;
-  out->X[0] = p + m;
-  out->X[1] = p + 2 * m;
-  out->R = p + 3 * m;
-  out->U[0] = depth >= 2 ? p + 4 * m : nullptr;
-  out->U[1] = depth >= 3 ? p + 5 * m : nullptr;
+  out->A = base + L.A;
+  out->X[0] = base + L.X0;
+  out->X[1] = base + L.X1;
+  out->R = base + L.R;
+  out->U[0] = L.U0 ? base + L.U0 : nullptr;
+  out->U[1] = L.U1 ? base + L.U1 : nullptr;
 }
 
 // Lay out an admitted request's first block: control region, then the start
@@ -270,27 +206,16 @@ void carve_phase(char* p, int64_t n, nn_dtype dt, int depth, PhaseBufs* out) {
 // wide phase if any.
 void carve_request(nn_server* s, Request* q) {
   char* b = s->pool + q->narrow.off;
-  const int cm = is_complex(q->dt) ? 2 : 1;
-  const int t64 = plan_gemm(Elem::F64, q->n, cm * q->n).num_tiles();
-  const int t32 = plan_gemm(Elem::F32, q->n, cm * q->n).num_tiles();
-  q->part = reinterpret_cast<double*>(b);
-  b += up(sizeof(double) * (size_t)std::max({t64, t32, 1}));
-  q->denpart = reinterpret_cast<double*>(b);
-  b += up(sizeof(double) * den_partials_elems(q->n));
-  q->pw = reinterpret_cast<double*>(b);
-  b += up(sizeof(double) * start_scratch_doubles(q->n));
-  q->scal = reinterpret_cast<double*>(b);
-  b += up(sizeof(double) * 8);
-  const int d = s->prm.depth;
-  if (single_dtype(q->dt)) {
-    carve_phase(b, q->n, q->dt, d, &q->ph[0]);
-    b += phase_bytes(q->n, q->dt, d);
-    if (q->reserve_wide) carve_phase(b, q->n, widen(q->dt), d, &q->ph[1]);
-    q->cur_ph = 0;
-  } else {
-    carve_phase(b, q->n, q->dt, d, &q->ph[1]);
-    q->cur_ph = 1;
-  }
+  const sched::ReqLayout L = sched::carve_block(sizes_of(q->n, q->dt, s->prm.depth),
+                                                q->reserve_wide);
+  q->part = reinterpret_cast<double*>(b + L.part);
+  q->denpart = reinterpret_cast<double*>(b + L.denpart);
+  q->pw = reinterpret_cast<double*>(b + L.pw);
+  q->scal = reinterpret_cast<double*>(b + L.scal);
+  if (L.narrow.used) set_phase(b, L.narrow, q->dt, &q->ph[0]);
+  if (L.wide.used) set_phase(b, L.wide, widen(q->dt), &q->ph[1]);
+  q->has_wide = L.wide.used;
+  q->cur_ph = L.narrow.used ? 0 : 1;
 }
 
 // Residual of the current iterate, rms into the request's slot.
@@ -306,8 +231,8 @@ hipError_t enqueue_residual(nn_server* s, Request* q) {
   return launch_rms_reduce(q->part, plan.num_tiles(), n, s->slots_dev + 2 * q->slot, st);
 }
 
-// Horner chain U_1 = R, U_{m+1} = R + R U_m, then X[cur^1] = X + X U_d.
-hipError_t enqueue_nest(nn_server* s, Request* q) {
+// Horner chain U_1 = R, U_{m+1} = R + R U_m, then X[from^1] = X + X U_d.
+hipError_t enqueue_nest(nn_server* s, Request* q, int from) {
   hipStream_t st = s->streams[q->stream];
   const PhaseBufs& P = q->ph[q->cur_ph];
   const bool cplx = is_complex(P.dt);
@@ -322,7 +247,7 @@ hipError_t enqueue_nest(nn_server* s, Request* q) {
     if (err != hipSuccess) return err;
     U = Un;
   }
-  GemmArgs g{P.X[q->cur], nr, U, nr, P.X[q->cur ^ 1], nr, P.X[q->cur], nr, n, nr, nr, 1.0, 0.0,
+  GemmArgs g{P.X[from], nr, U, nr, P.X[from ^ 1], nr, P.X[from], nr, n, nr, nr, 1.0, 0.0,
              nullptr};
   return launch_gemm(e, cplx, plan, g, st);
 }
@@ -346,7 +271,8 @@ hipError_t enqueue_start(nn_server* s, Request* q) {
   return q->small ? hipSuccess : enqueue_residual(s, q);
 }
 
-// Widen A and the iterate X[from] into the wide phase, then its residual.
+// Widen A and the narrow iterate X[from] into the wide phase's X[0] (the
+// policy has already switched q to the wide phase), then its residual.
 hipError_t enqueue_promote(nn_server* s, Request* q, int from) {
   hipStream_t st = s->streams[q->stream];
   const PhaseBufs& N = q->ph[0];
@@ -358,10 +284,6 @@ hipError_t enqueue_promote(nn_server* s, Request* q, int from) {
   err = launch_cast_f32_f64(static_cast<const float*>(N.X[from]), nr,
                             static_cast<double*>(W.X[0]), nr, n, nr, st);
   if (err != hipSuccess) return err;
-  q->cur_ph = 1;
-  q->cur = 0;
-  q->phase_k = 0;
-  q->rms_prev = NAN;
   return enqueue_residual(s, q);
 }
 
@@ -371,11 +293,10 @@ void release_blocks(nn_server* s, Request* q) {
   q->narrow.held = q->wide.held = false;
 }
 
-void retire(nn_server* s, Request* q, int32_t status, double rms, int result_buf) {
-  q->status = status;
-  q->rms = rms;
-  q->result_buf = result_buf;
-  q->state = State::Retired;
+// Bookkeeping of a request the policy retired (status, rms and result_buf
+// are set on it).
+void retire(nn_server* s, Request* q) {
+  q->state = RState::Retired;
   q->t_finish = s->now();
   s->free_slots.push(q->slot);
   q->slot = -1;
@@ -385,49 +306,43 @@ void retire(nn_server* s, Request* q, int32_t status, double rms, int result_buf
 
 // Try to reserve the wide block of a request that did not reserve it.
 bool reserve_wide_late(nn_server* s, Request* q) {
-  if (q->ph[1].A) return true;
-  const size_t b = up(phase_bytes(q->n, widen(q->dt), s->prm.depth));
+  if (q->has_wide) return true;
+  const size_t mat = (size_t)q->n * (size_t)q->n * elem_size(widen(q->dt));
+  const size_t b = up(sched::phase_bytes(mat, s->prm.depth));
   size_t off;
   if (!s->alloc.alloc(b, &off)) return false;
   q->wide = {off, b, true};
-  carve_phase(s->pool + off, q->n, widen(q->dt), s->prm.depth, &q->ph[1]);
+  set_phase(s->pool + off, sched::carve_phase(mat, s->prm.depth, 0), widen(q->dt), &q->ph[1]);
+  q->has_wide = true;
   return true;
 }
 
 nn_status admit(nn_server* s) {
-  int scanned = 0;
-  bool head_blocked = false;
-  for (auto it = s->queued.begin(); it != s->queued.end() && scanned < kBypassScan;) {
-    if ((int)s->active.size() >= s->prm.max_active) break;
-    Request* q = *it;
-    ++scanned;
+  hipError_t err = hipSuccess;
+  auto try_alloc = [&](sched::Req* r) {
+    if (err != hipSuccess) return false;  // stop admitting after a failed launch
+    Request* q = static_cast<Request*>(r);
     size_t off;
     const size_t b = footprint_of(s, q->n, q->dt, q->tol, &q->reserve_wide);
-    if (!s->alloc.alloc(b, &off)) {
-      if (!head_blocked) {
-        head_blocked = true;
-        // A request passed over too often holds the line: admit nothing after it.
-        if (q->bypassed >= kMaxBypassTicks) break;
-        ++q->bypassed;
-      }
-      ++it;
-      continue;
-    }
+    if (!s->alloc.alloc(b, &off)) return false;
     q->narrow = {off, b, true};
+    return true;
+  };
+  auto on_admit = [&](sched::Req* r) {
+    Request* q = static_cast<Request*>(r);
     carve_request(s, q);
     q->slot = s->free_slots.top();
     s->free_slots.pop();
     q->stream = s->rr++ % s->n_streams;
-    q->state = State::Active;
-    q->fresh = true;
     q->small = small_path(s, q->n, q->dt, q->max_iter);
     q->t_admit = s->now();
-    HIP_TRY(enqueue_start(s, q));
     if (q->small) s->small_new.push_back(q);
     s->active.push_back(q);
-    it = s->queued.erase(it);
-  }
-  return NN_OK;
+    const hipError_t e = enqueue_start(s, q);
+    if (err == hipSuccess) err = e;
+  };
+  sched::admit_scan(s->queued, s->active.size(), s->prm.max_active, try_alloc, on_admit);
+  return err == hipSuccess ? NN_OK : NN_ERR_HIP;
 }
 
 // One batched launch per dtype over the requests admitted to the small path
@@ -448,7 +363,7 @@ nn_status launch_small(nn_server* s) {
   double* tols = reinterpret_cast<double*>(s->bhost + L.tols);
   int32_t* sizes = reinterpret_cast<int32_t*>(s->bhost + L.sizes);
   int32_t* maxits = reinterpret_cast<int32_t*>(s->bhost + L.maxits);
-  const double point = pow(1e-9, 1.0 / (s->prm.depth + 1));
+  const double point = sched::promotion_point(s->prm.depth);
   int j = 0;
   int first[2] = {0, 0}, count[2] = {0, 0}, maxn[2] = {0, 0};
   const nn_dtype dts[2] = {NN_F32, NN_C64};
@@ -498,96 +413,31 @@ nn_status launch_small(nn_server* s) {
   return NN_OK;
 }
 
-// The batched narrow phase's record of a small request: retire it, or
-// promote it to the wide phase (which continues tick by tick).
-nn_status step_small(nn_server* s, Request* q, bool* keep) {
-  const BatchLayout L = batch_layout(s->prm.max_active);
-  const nn_info_dev r = reinterpret_cast<const nn_info_dev*>(s->bhost + L.info)[q->bidx];
-  q->small = false;
-  q->bidx = -1;
-  q->iters = r.iters;
-  q->phase_k = r.iters;
-  q->cur = 0;  // the batched launch leaves its result in X[0]
-  *keep = false;
-  const bool ok_narrow = r.status == NN_OK && r.rms < q->tol;
-  const bool promote = (r.status == NN_OK && !ok_narrow) || r.status == NN_STAGNATED;
-  if (promote && reserve_wide_late(s, q)) {
-    HIP_TRY(enqueue_promote(s, q, 0));
-    *keep = true;
-    return NN_OK;
-  }
-  // OK, or a stagnation that cannot be promoted (the OK-above-tolerance case
-  // always has its wide buffers, reserved at admission).
-  retire(s, q, r.status, r.rms, 0);
-  return NN_OK;
-}
-
-// Apply the rules to one active request whose rms (and den, if fresh) are in
-// the read-back.  Returns false if it retired.
+// Apply the policy to one active request whose rms (and den, if fresh) or
+// batched record are in the read-back, and enqueue what it decided.
 nn_status step_request(nn_server* s, Request* q, bool* keep) {
   const double* h = s->slots_host + 2 * q->slot;
-  *keep = false;
-  if (q->fresh) {
-    q->fresh = false;
-    const double den = h[1];
-    if (!isfinite(den) || den <= 0.0) {
-      q->small = false;
-      retire(s, q, isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE, NAN, q->cur);
-      return NN_OK;
-    }
+  const nn_info_dev* rec = nullptr;
+  if (q->small) {
+    const BatchLayout L = batch_layout(s->prm.max_active);
+    rec = reinterpret_cast<const nn_info_dev*>(s->bhost + L.info) + q->bidx;
+    q->bidx = -1;
   }
-  if (q->small) return step_small(s, q, keep);
-  const double rms = h[0];
-  const bool narrow = q->cur_ph == 0;
-  const double sqn = sqrt((double)q->n);
-  if (!isfinite(rms)) {
-    retire(s, q, NN_ERR_NONFINITE, rms, q->cur);
-    return NN_OK;
+  auto try_wide = [s](sched::Req& r) { return reserve_wide_late(s, static_cast<Request*>(&r)); };
+  const sched::Decision dd = sched::decide(*q, h[0], h[1], s->prm.depth, try_wide, rec);
+  *keep = dd.act != sched::Act::Retire;
+  switch (dd.act) {
+    case sched::Act::Retire:
+      retire(s, q);
+      break;
+    case sched::Act::Promote:
+      HIP_TRY(enqueue_promote(s, q, dd.from));
+      break;
+    case sched::Act::Nest:
+      HIP_TRY(enqueue_nest(s, q, dd.from));
+      HIP_TRY(enqueue_residual(s, q));
+      break;
   }
-  if (rms < q->tol) {
-    retire(s, q, NN_OK, rms, q->cur);
-    return NN_OK;
-  }
-  if (q->phase_k > 0 && rms >= 1.0 && rms > q->rms_prev) {
-    retire(s, q, NN_ERR_DIVERGED, rms, q->cur);
-    return NN_OK;
-  }
-  const bool stagnated = q->phase_k > 0 && sqn * q->rms_prev < 0.1 && rms >= q->rms_prev;
-  if (narrow) {
-    const double point = pow(1e-9, 1.0 / (s->prm.depth + 1));
-    const bool early = q->reserve_wide && q->phase_k > 0 && q->rms_prev < point;
-    if (early || stagnated) {
-      if (reserve_wide_late(s, q)) {
-        const bool back = q->phase_k > 0 && q->rms_prev <= rms;  // continue from X_{k-1}
-        if (back) --q->iters;
-        HIP_TRY(enqueue_promote(s, q, back ? q->cur ^ 1 : q->cur));
-        *keep = true;
-        return NN_OK;
-      }
-      if (stagnated) {
-        --q->iters;
-        retire(s, q, NN_STAGNATED, q->rms_prev, q->cur ^ 1);
-        return NN_OK;
-      }
-    }
-  } else if (stagnated) {
-    --q->iters;
-    --q->wide_iters;
-    retire(s, q, NN_STAGNATED, q->rms_prev, q->cur ^ 1);
-    return NN_OK;
-  }
-  if (q->iters >= q->max_iter) {
-    retire(s, q, NN_NOT_CONVERGED, rms, q->cur);
-    return NN_OK;
-  }
-  q->rms_prev = rms;
-  HIP_TRY(enqueue_nest(s, q));
-  q->cur ^= 1;
-  ++q->iters;
-  ++q->phase_k;
-  if (!narrow) ++q->wide_iters;
-  HIP_TRY(enqueue_residual(s, q));
-  *keep = true;
   return NN_OK;
 }
 
@@ -602,7 +452,7 @@ void fill_stats(const nn_server* s, int fin, nn_server_stats* st) {
 
 Request* find_retired(nn_server* s, int64_t id) {
   auto it = s->by_id.find(id);
-  if (it == s->by_id.end() || it->second->state != State::Retired) return nullptr;
+  if (it == s->by_id.end() || it->second->state != RState::Retired) return nullptr;
   return it->second;
 }
 

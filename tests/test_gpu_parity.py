@@ -111,14 +111,16 @@ def test_ragged_sizes_fp64(n, ld):
 
 
 @pytest.mark.parametrize("tile", ["T128", "T128W8", "T128K8", "T128W8K8", "T256K8", "T256",
-                                  "T64", "T32"])
+                                  "T64", "T32", "T16"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32, np.complex128, np.complex64])
-@pytest.mark.parametrize("n", [197, 256])
+@pytest.mark.parametrize("n", [197, 256, 320])
 def test_every_tile_config(tile, dtype, n, monkeypatch):
     """Each GEMM tile configuration, forced for every product, on a size with
     ragged tails in both dimensions (n = 197: the bounds-checked kernels) and
     on one every tile divides (n = 256: the kernels without bounds checks),
-    each with an odd leading dimension too."""
+    and on one whose k extent is not a multiple of the small-product kernel's
+    64-deep chunks (n = 320, complex k = 640 is), each with an odd leading
+    dimension too."""
     _say(f"tile {tile} {np.dtype(dtype).name} n={n}")
     monkeypatch.setenv("NN_GEMM_TILE", tile)
     cplx = np.dtype(dtype).kind == "c"
