@@ -76,6 +76,13 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 1 GiB device copies (untimed), the reference "
                          "kernel for scaling HBM counters")
+    ap.add_argument("--batched-reps", type=int, default=50,
+                    help="timed replays per start in the batched leg")
+    ap.add_argument("--profile-report", nargs="+", metavar="DIR",
+                    help="no GPU work: summarise the rocprofv3 CSV output under each DIR "
+                         "(kernel statistics, counter means per kernel, and the HBM traffic "
+                         "per FP64 GEMM launch when FETCH_SIZE / WRITE_SIZE and the copy "
+                         "calibration are present), then exit")
     return ap.parse_args()
 
 
@@ -97,6 +104,68 @@ def traffic_per_launch(n):
     if rec.get("gemm_source_sha256") != sha or rec.get("n") != n:
         return None
     return rec["hbm_bytes_per_launch"]
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def profile_report(dirs, n=8192):
+    """Print a summary of rocprofv3 output (--kernel-trace --stats and --pmc
+    runs with --output-format csv) found under dirs."""
+    import glob
+    import hashlib
+    stats, counters = [], {}
+    for d in dirs:
+        for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+            stats += _csv_rows(path)
+        for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"),
+                                     recursive=True)):
+            per = {}  # (kernel, dispatch, counter) -> summed value
+            for r in _csv_rows(path):
+                key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id", "")),
+                       r["Counter_Name"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+            for (k, _, c), v in per.items():
+                counters.setdefault(k, {}).setdefault(c, []).append(v)
+    if stats:
+        print("kernel statistics (rocprofv3 --stats): calls, average / min / max duration")
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+            print(f"  {int(r['Calls']):7d}  avg {float(r['AverageNs']) / 1e3:11.2f} us  "
+                  f"min {float(r['MinNs']) / 1e3:11.2f}  max {float(r['MaxNs']) / 1e3:11.2f}  "
+                  f"{float(r['Percentage']):5.1f}%  {r['Name'][:150]}")
+    for k, cs in counters.items():
+        print(f"counters per dispatch: {k[:150]}")
+        for c, vals in sorted(cs.items()):
+            print(f"  {c:32s} dispatches {len(vals):4d}  mean {sum(vals) / len(vals):16.1f}  "
+                  f"min {min(vals):16.1f}")
+    # HBM traffic of the FP64 GEMM, each counter scaled by its reading for a
+    # plain 1 GiB device copy (1 GiB read and 1 GiB written)
+    copy = [k for k in counters if "copyBuffer" in k]
+    gemm = [k for k in counters if k.startswith("void nn::(anonymous namespace)::gemm_kernel<double")]
+    if copy and gemm:
+        cc, gc = counters[copy[0]], counters[gemm[0]]
+        if all(c in cc and c in gc for c in ("FETCH_SIZE", "WRITE_SIZE")):
+            kib = 1024.0 * 1024.0
+            big = lambda v: [x for x in v if x > 0.25 * kib]  # noqa: E731  (the 1 GiB copies)
+            f_copy = sum(big(cc["FETCH_SIZE"])) / max(len(big(cc["FETCH_SIZE"])), 1)
+            w_copy = sum(big(cc["WRITE_SIZE"])) / max(len(big(cc["WRITE_SIZE"])), 1)
+            sf, sw = kib / f_copy, kib / w_copy
+            f = sum(gc["FETCH_SIZE"]) / len(gc["FETCH_SIZE"])
+            w = sum(gc["WRITE_SIZE"]) / len(gc["WRITE_SIZE"])
+            hbm = (f * sf + w * sw) * 1024.0
+            alg = 3 * 8 * n * n
+            sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+            rec = {"kernel": gemm[0][len("void nn::(anonymous namespace)::"):].split("(")[0],
+                   "n": n, "launches": len(gc["FETCH_SIZE"]), "fetch_kib_per_launch_raw": f,
+                   "write_kib_per_launch_raw": w, "copy_scale_fetch": sf, "copy_scale_write": sw,
+                   "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg,
+                   "traffic_over_algorithmic": hbm / alg, "gemm_source_sha256": sha}
+            print(f"FP64 GEMM HBM traffic per launch: {hbm / 1e9:.3f} GB (FETCH_SIZE x {sf:.4f} + "
+                  f"WRITE_SIZE x {sw:.4f}), algorithmic {alg / 1e9:.3f} GB, ratio {hbm / alg:.2f}")
+            print("json: " + json.dumps(rec))
 
 
 def time_inversions(nn, torch, A, steps, warmup, **kw):
@@ -263,7 +332,7 @@ def leg_small(nn, torch, workloads, np, n=256, reps=200, oracle_reps=5):
     return out
 
 
-def leg_batched(nn, torch, workloads, np):
+def leg_batched(nn, torch, workloads, np, reps=50):
     """4096 massive-MIMO Gram matrices G = H^H H + 0.1 I (H 128 x K, K in
     {8,16,32,64}), complex64, depth 2, 4 fixed nests, one graph launch."""
     packed, offsets, sizes, mats = workloads.mimo_gram_batch(batch=4096, seed=3)
@@ -280,7 +349,6 @@ def leg_batched(nn, torch, workloads, np):
         for _ in range(3):
             nn.invert_batched(P, O, S, 64, x0=x0, fixed_iter=4, X=X, info=info, ws=hold)
         torch.cuda.synchronize()
-        reps = 50
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(reps):
@@ -660,6 +728,9 @@ def leg_serving(nn, torch, workloads, np, pool_size, n_req, window_s=30.0, overl
 
 def main():
     args = parse()
+    if args.profile_report:
+        profile_report(args.profile_report, args.n)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU: --gpus must be 1; "
                                    "more GPUs are not supported"}))
@@ -755,7 +826,7 @@ def main():
         del X
         torch.cuda.empty_cache()
     if "batched" in legs:
-        extra["batched"] = leg_batched(nn, torch, workloads, np)
+        extra["batched"] = leg_batched(nn, torch, workloads, np, args.batched_reps)
     if "mixed" in legs:
         extra["mixed"] = leg_mixed(nn, torch, workloads, np, args.mixed_n, args.host_input)
         torch.cuda.empty_cache()

@@ -158,7 +158,12 @@ def test_mixed_preconditioner_fp64_series():
     assert p["status"] == nn.NN_OK and p["rms"] < 1e-2 and p["phase_iters"][2] == 0
     x = X.cpu().numpy()
     assert _relF(x, np.linalg.solve(A, B)) <= 1e3 * info["rms"] * 1.01 + 1e-13
-    assert abs(np.linalg.norm(B - A @ x) / np.linalg.norm(B) - info["rms"]) <= 1e-6 * info["rms"] + 1e-15
+    # the reported rms is the relative residual of the returned X, up to the
+    # rounding of forming B - A x in FP64 in two summation orders (host and
+    # device): about sqrt(n) u || |A| |x| || / ||B|| (probabilistic bound)
+    u = np.finfo(np.float64).eps / 2
+    fl = 2 * np.sqrt(n) * u * np.linalg.norm(np.abs(A) @ np.abs(x)) / np.linalg.norm(B)
+    assert abs(np.linalg.norm(B - A @ x) / np.linalg.norm(B) - info["rms"]) <= 1e-6 * info["rms"] + fl
 
 
 def test_statuses_and_arguments():
