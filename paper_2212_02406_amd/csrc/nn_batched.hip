@@ -71,6 +71,18 @@ __device__ __host__ __forceinline__ int lds_buf(int K, bool cplx) {
   return pad16(K) * lds_ld(K, cplx);
 }
 
+// Column swizzle of complex rows: when a row's padded width is a multiple of
+// 32 floats, rows 2 and 3 mod 4 store column c at c ^ 16.  With ld = 4 mod 32
+// the B-fragment reads of a k-group (8-byte pairs of complex rows 2 lk and
+// 2 lk + 1 for lane quarter lk, 32 lanes at a time) otherwise put lane
+// quarters 0 and 1 on overlapping banks (row offset 2 ld = 8 mod 64); the
+// swizzle moves one of them 16 banks away.  16-byte segments stay whole (bit
+// 4 only) and the A-fragment reads stay conflict free.  swz: 0 or 16.
+__device__ __host__ __forceinline__ int lds_swz(int K, bool cplx) {
+  return cplx && (pad16(2 * K) & 31) == 0 ? 16 : 0;
+}
+__device__ __forceinline__ int scol(int r, int c, int swz) { return c ^ (((r >> 1) & 1) * swz); }
+
 // Dynamic LDS of the persistent kernel (matrix buffers) and the per-group
 // reduction scratch.  Everything below addresses LDS through these arrays and
 // integer offsets, so the accesses compile to ds_read/ds_write.
@@ -113,10 +125,10 @@ struct KFrag {
 
 template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB, SH>& f, const int* aoff,
-                                            const int* boff, int j, int ld) {
+                                            const int* boff, int j, int ld, int sa) {
 #pragma unroll
   for (int i = 0; i < (SH ? 1 : NB); ++i)
-    f.a[i] = *reinterpret_cast<const f4_t*>(&smem[aoff[i] + 16 * j]);
+    f.a[i] = *reinterpret_cast<const f4_t*>(&smem[aoff[i] + ((16 * j) ^ sa)]);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if constexpr (CPLX) {
@@ -131,31 +143,34 @@ __device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB, SH>& f, const int* a
   }
 }
 
+// The four MFMA steps of a k-group, step-major over the blocks: consecutive
+// MFMAs write different accumulators, so one does not wait for the previous
+// one's result (each accumulator still sums its k in the same order).
 template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB, SH>& f,
                                            const bool* even) {
+  float b[NB][4];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const f4_t a = f.a[SH ? 0 : i];
-    float b0, b1, b2, b3;
     if constexpr (CPLX) {
       // expanded rows 2 kc, 2 kc + 1 of two complex rows kc0, kc0 + 1
       const bool ev = even[i];
-      b0 = ev ? f.b[i].x : f.b[i].y;
-      b1 = ev ? -f.b[i].y : f.b[i].x;
-      b2 = ev ? f.b[i].z : f.b[i].w;
-      b3 = ev ? -f.b[i].w : f.b[i].z;
+      b[i][0] = ev ? f.b[i].x : f.b[i].y;
+      b[i][1] = ev ? -f.b[i].y : f.b[i].x;
+      b[i][2] = ev ? f.b[i].z : f.b[i].w;
+      b[i][3] = ev ? -f.b[i].w : f.b[i].z;
     } else {
-      b0 = f.b[i].x;
-      b1 = f.b[i].y;
-      b2 = f.b[i].z;
-      b3 = f.b[i].w;
+      b[i][0] = f.b[i].x;
+      b[i][1] = f.b[i].y;
+      b[i][2] = f.b[i].z;
+      b[i][3] = f.b[i].w;
     }
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b0, acc[i], 0, 0, 0);
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b1, acc[i], 0, 0, 0);
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b2, acc[i], 0, 0, 0);
-    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b3, acc[i], 0, 0, 0);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[SH ? 0 : i][q], b[i][q], acc[i], 0, 0, 0);
 }
 
 // C = alpha * A B + E + diag * I on K x K matrices held in LDS at float
@@ -177,11 +192,14 @@ __device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB, SH>&
 template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, int ld,
                                             float alpha, float diag, const Group& g,
-                                            double* ss) {
+                                            double* ss, int swz) {
   const int cols = CPLX ? 2 * K : K;
   const int nbm = (K + 15) >> 4, nbn = (cols + 15) >> 4, nb = nbm * nbn;
   const int first = g.gw * NB;
   const int lr = g.lane & 15, lk = g.lane >> 4;
+  // swizzle of this lane's A rows (bm 16 + lr) and B rows (complex 8 j + 2 lk
+  // and + 1): fixed per lane
+  const int sa = ((lr >> 1) & 1) * swz, sb = (lk & 1) * swz;
   f4_t acc[NB];
   int aoff[NB], boff[NB], bm_[NB], bn_[NB];
   bool even[NB], live[NB];
@@ -195,7 +213,7 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
     const int n = bn_[i] * 16 + lr;
     aoff[i] = A + (bm_[i] * 16 + lr) * ld + 4 * lk;
     if constexpr (CPLX) {
-      boff[i] = B + (2 * lk) * ld + (n & ~1);
+      boff[i] = B + (2 * lk) * ld + ((n & ~1) ^ sb);
       even[i] = !(n & 1);
     } else {
       boff[i] = B + (4 * lk) * ld + n;
@@ -205,7 +223,7 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
   const int kgroups = nbn;  // padded real inner dimension / 16
   for (int j = 0; j < kgroups; ++j) {
     KFrag<CPLX, NB, SH> f;
-    load_kgroup<CPLX, NB, SH>(f, aoff, boff, j, ld);  // all operand reads of the group first
+    load_kgroup<CPLX, NB, SH>(f, aoff, boff, j, ld, sa);  // all operand reads of the group first
     mma_kgroup<CPLX, NB, SH>(acc, f, even);
   }
   // Epilogue in registers (rows 4 (lane/16) + t of each block, FP32 layout).
@@ -218,7 +236,7 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
       const int m = bm_[i] * 16 + 4 * lk + t;
       if (live[i] && m < K && n < cols) {
         float v = alpha * acc[i][t];
-        if (E >= 0) v += smem[E + m * ld + n];
+        if (E >= 0) v += smem[E + m * ld + scol(m, n, swz)];
         if (CPLX ? (n == 2 * m) : (n == m)) v += diag;
         acc[i][t] = v;
         s += (double)v * (double)v;
@@ -232,7 +250,7 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int m = bm_[i] * 16 + 4 * lk + t;
-      if (live[i] && m < K && n < cols) smem[C + m * ld + n] = acc[i][t];
+      if (live[i] && m < K && n < cols) smem[C + m * ld + scol(m, n, swz)] = acc[i][t];
     }
   }
   if (ss) {
@@ -251,7 +269,7 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
 
 // Blocks per wave for a K x K product over G waves, rounded up to 1, 2, 4 or
 // 8 (the kernel is instantiated for those counts only).
-__device__ __forceinline__ int blocks_per_wave(int K, bool cplx, int G) {
+__device__ __host__ __forceinline__ int blocks_per_wave(int K, bool cplx, int G) {
   const int cols = cplx ? 2 * K : K;
   const int nb = ((K + 15) >> 4) * ((cols + 15) >> 4);
   const int per = (nb + G - 1) / G;
@@ -285,6 +303,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
                                            int bufstride, const Group& g, nn_info_dev* info) {
   const int cols = CPLX ? 2 * K : K;
   const int ld = lds_ld(K, CPLX);
+  const int swz = lds_swz(K, CPLX);
   const int Xs = buf, Rs = buf + bufstride, Us = depth >= 3 ? buf + 2 * bufstride : Rs;
   const int Gs = Rs;  // G is staged into R's buffer
   double* red = s_red[g.redrow];
@@ -299,12 +318,12 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   // over columns (coalesced, no index division)
   auto stage_g = [&]() {
     for (int r = g.gw; r < K; r += g.G)
-      for (int c = g.lane; c < cols; c += 64) smem[Gs + r * ld + c] = Ag[r * cols + c];
+      for (int c = g.lane; c < cols; c += 64) smem[Gs + r * ld + scol(r, c, swz)] = Ag[r * cols + c];
     g.sync();
   };
   auto store_x = [&]() {
     for (int r = g.gw; r < K; r += g.G)
-      for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + c];
+      for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + scol(r, c, swz)];
   };
   stage_g();
   // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G;
@@ -318,7 +337,8 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       for (int j = 0; j < K; ++j) {
         const int r = row ? i : j, c = row ? j : i;
         if constexpr (CPLX) {
-          const double re = smem[Gs + r * ld + 2 * c], im = smem[Gs + r * ld + 2 * c + 1];
+          const double re = smem[Gs + r * ld + scol(r, 2 * c, swz)];
+          const double im = smem[Gs + r * ld + scol(r, 2 * c + 1, swz)];
           s += sqrt(re * re + im * im);
         } else {
           s += fabs((double)smem[Gs + r * ld + c]);
@@ -338,7 +358,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     den = bad ? NAN : n1 * ninf;
   } else if (x0 == NN_X0_SCALED_IDENTITY) {
     double t = 0.0;
-    for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + (CPLX ? 2 * i : i)];
+    for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + scol(i, CPLX ? 2 * i : i, swz)];
     den = t;
   }
   const bool den_ok = isfinite(den) && den > 0.0;
@@ -346,7 +366,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   g.sync();
   if (x0 == NN_X0_GIVEN) {
     for (int r = g.gw; r < K; r += g.G)
-      for (int c = g.lane; c < cols; c += 64) smem[Xs + r * ld + c] = Xg[r * cols + c];
+      for (int c = g.lane; c < cols; c += 64) smem[Xs + r * ld + scol(r, c, swz)] = Xg[r * cols + c];
   } else {
     for (int e = g.gtid; e < K * cols; e += nthr) {
       const int r = e / cols, c = e - r * cols;
@@ -354,14 +374,15 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       if (x0 == NN_X0_TRANSPOSE) {
         if constexpr (CPLX) {
           const int j = c >> 1;  // X[r][j] = conj(G[j][r]) * s
-          v = (c & 1) ? -smem[Gs + j * ld + 2 * r + 1] * s : smem[Gs + j * ld + 2 * r] * s;
+          v = (c & 1) ? -smem[Gs + j * ld + scol(j, 2 * r + 1, swz)] * s
+                      : smem[Gs + j * ld + scol(j, 2 * r, swz)] * s;
         } else {
           v = smem[Gs + c * ld + r] * s;
         }
       } else {
         v = (CPLX ? (c == 2 * r) : (c == r)) ? s : 0.f;
       }
-      smem[Xs + r * ld + c] = v;
+      smem[Xs + r * ld + scol(r, c, swz)] = v;
     }
   }
   g.sync();
@@ -377,7 +398,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       if (k > 0) stage_g();  // the first residual finds G staged by the start
       double ss = 0.0;
       const bool want = !fixed || k == iters;
-      lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, want ? &ss : nullptr);  // R = I - G X
+      lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, want ? &ss : nullptr, swz);  // R = I - G X
       if (fixed) {
         if (k == iters) {
           rms = sqrt(ss / (double)K);
@@ -409,10 +430,10 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       }
       int U = Rs;
       for (int m = 1; m < depth; ++m) {  // U_{m+1} = R + R U_m
-        lds_gemm_nb<CPLX, NB, SH>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr);
+        lds_gemm_nb<CPLX, NB, SH>(Rs, U, Rs, Us, K, ld, 1.f, 0.f, g, nullptr, swz);
         U = Us;
       }
-      lds_gemm_nb<CPLX, NB, SH>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr);  // X = X + X U
+      lds_gemm_nb<CPLX, NB, SH>(Xs, U, Xs, Xs, K, ld, 1.f, 0.f, g, nullptr, swz);  // X = X + X U
       rms_prev = rms;
       ++k;
     }
@@ -489,7 +510,14 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
 // 1 KB of scratch spills per lane).  TOL selects the control mode at compile
 // time (tolerance mode, a.iters == 0, or a fixed number of nests), so the
 // fixed-nest kernel carries none of the per-nest stopping logic.
-template <bool CPLX, bool TOL>
+// MAXNB: the largest blocks-per-wave count compiled in (4 or 8).  The 8-block
+// paths (one-wave complex matrices of K in 17..32, only reachable with a
+// one-wave limit of 32) hold the most registers; compiling them only when a
+// launch can reach them takes the other launches from 682 spilled registers
+// per lane to about 120 (gfx950, 128-register budget).  The host picks the
+// instantiation (batched_max_nb); an item that would need more blocks than
+// compiled in is reported as unsupported rather than computed.
+template <bool CPLX, bool TOL, int MAXNB>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
   __shared__ int item_s;
@@ -528,8 +556,14 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
         case 5: NN_ONE(2, true); break;
         case 8: NN_ONE(4, false); break;
         case 9: NN_ONE(4, true); break;
-        case 17: NN_ONE(8, true); break;
-        default: NN_ONE(8, false); break;
+        case 17:
+          if constexpr (MAXNB >= 8) NN_ONE(8, true);
+          else if (inf && tid == 0) *inf = nn_info_dev{0, NN_ERR_UNSUPPORTED, NAN};
+          break;
+        default:
+          if constexpr (MAXNB >= 8) NN_ONE(8, false);
+          else if (inf && tid == 0) *inf = nn_info_dev{0, NN_ERR_UNSUPPORTED, NAN};
+          break;
       }
 #undef NN_ONE
     } else {
@@ -555,8 +589,14 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
           case 5: NN_ONE(2, true); break;
           case 8: NN_ONE(4, false); break;
           case 9: NN_ONE(4, true); break;
-          case 17: NN_ONE(8, true); break;
-          default: NN_ONE(8, false); break;
+          case 17:
+            if constexpr (MAXNB >= 8) NN_ONE(8, true);
+            else if (inf && lane == 0) *inf = nn_info_dev{0, NN_ERR_UNSUPPORTED, NAN};
+            break;
+          default:
+            if constexpr (MAXNB >= 8) NN_ONE(8, false);
+            else if (inf && lane == 0) *inf = nn_info_dev{0, NN_ERR_UNSUPPORTED, NAN};
+            break;
         }
 #undef NN_ONE
       }
@@ -588,18 +628,33 @@ hipError_t launch_batched(const BatchedArgs& args, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = lds_bytes(cplx, a.max_n, a.wave_max_k, a.depth);
+  const bool nb8 = batched_max_nb(cplx, a.max_n, a.wave_max_k) > 4;
+  const dim3 grid(a.grid), block(kThreads);
+#define NN_LAUNCH(C, T)                                                                 \
+  do {                                                                                  \
+    if (nb8)                                                                            \
+      hipLaunchKernelGGL((batched_nn<C, T, 8>), grid, block, lds, s, a, perm, hdr);      \
+    else                                                                                \
+      hipLaunchKernelGGL((batched_nn<C, T, 4>), grid, block, lds, s, a, perm, hdr);      \
+  } while (0)
   if (cplx) {
-    if (a.iters > 0)
-      hipLaunchKernelGGL((batched_nn<true, false>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
-    else
-      hipLaunchKernelGGL((batched_nn<true, true>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
+    if (a.iters > 0) NN_LAUNCH(true, false);
+    else NN_LAUNCH(true, true);
   } else {
-    if (a.iters > 0)
-      hipLaunchKernelGGL((batched_nn<false, false>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
-    else
-      hipLaunchKernelGGL((batched_nn<false, true>), dim3(a.grid), dim3(kThreads), lds, s, a, perm, hdr);
+    if (a.iters > 0) NN_LAUNCH(false, false);
+    else NN_LAUNCH(false, true);
   }
+#undef NN_LAUNCH
   return hipGetLastError();
+}
+
+int batched_max_nb(bool cplx, int max_n, int wave_max_k) {
+  int m = 1;
+  for (int K = 1; K <= max_n && K <= kMaxN; ++K) {
+    const int nb = blocks_per_wave(K, cplx, K <= wave_max_k ? 1 : kWaves);
+    m = nb > m ? nb : m;
+  }
+  return m;
 }
 
 size_t batched_static_lds() {
@@ -608,7 +663,7 @@ size_t batched_static_lds() {
   static size_t cached = 0;
   if (!cached) {
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&batched_nn<true, false>)) ==
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&batched_nn<true, false, 4>)) ==
             hipSuccess &&
         fa.sharedSizeBytes > 0)
       cached = fa.sharedSizeBytes;
@@ -630,10 +685,14 @@ int batched_fit_wave_max_k(nn_dtype dt, int max_n, int wave_max_k, int depth) {
 
 hipError_t batched_allow_lds() {
   const int lim = (int)kBatchedDynLds;  // dynamic part; the static part is batched_static_lds()
-  const void* kernels[4] = {reinterpret_cast<const void*>(&batched_nn<true, false>),
-                            reinterpret_cast<const void*>(&batched_nn<true, true>),
-                            reinterpret_cast<const void*>(&batched_nn<false, false>),
-                            reinterpret_cast<const void*>(&batched_nn<false, true>)};
+  const void* kernels[8] = {reinterpret_cast<const void*>(&batched_nn<true, false, 4>),
+                            reinterpret_cast<const void*>(&batched_nn<true, true, 4>),
+                            reinterpret_cast<const void*>(&batched_nn<false, false, 4>),
+                            reinterpret_cast<const void*>(&batched_nn<false, true, 4>),
+                            reinterpret_cast<const void*>(&batched_nn<true, false, 8>),
+                            reinterpret_cast<const void*>(&batched_nn<true, true, 8>),
+                            reinterpret_cast<const void*>(&batched_nn<false, false, 8>),
+                            reinterpret_cast<const void*>(&batched_nn<false, true, 8>)};
   for (const void* k : kernels) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;

@@ -212,6 +212,9 @@ struct BatchedArgs {
   int grid = 1;
 };
 hipError_t launch_batched(const BatchedArgs& a, hipStream_t s);
+// The largest blocks-per-wave count any matrix of size <= max_n takes (one
+// wave up to wave_max_k, a whole workgroup above): 1, 2, 4 or 8.
+int batched_max_nb(bool cplx, int max_n, int wave_max_k);
 
 // Upper bound of max_iter for the batched tolerance mode (bounds the
 // persistent kernel's run time).
