@@ -201,9 +201,9 @@ nn_status nn_invert(nn_ctx* ctx, const void* A, int64_t lda, void* X, int64_t ld
  *   Arguments, results and status codes as for nn_invert, plus:
  *   NN_ERR_WORKSPACE  nn_workspace_size(n, dtype, params) exceeds
  *                     NN_NOALLOC_SCRATCH_BYTES (plain FP64 / complex64 up to
- *                     n = 1441, 1178, 1021 at depths 1, 2, 3; FP32 up to
- *                     2031, 1662, 1441; complex128 up to 1021, 834, 722;
- *                     mixed FP64 at depth 2 up to 700); nothing is launched
+ *                     n = 1437, 1176, 1013 at depths 1, 2, 3; FP32 up to
+ *                     2019, 1656, 1437; complex128 up to 1013, 830, 720;
+ *                     mixed FP64 at depth 2 up to 698); nothing is launched
  *                     and X is untouched.
  *   NN_ERR_ARG        also for params->flags with NN_FLAG_TIME_GEMMS.
  * Every call on one device shares that device's array and leaves its contents

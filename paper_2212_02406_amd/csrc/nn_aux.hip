@@ -44,15 +44,21 @@ __global__ void __launch_bounds__(256) row_abs_sums(const T* A, int64_t lda, int
   if (lane == 0) rowsum[r] = s;
 }
 
-// Column partial sums over row chunks of kColChunk rows.
-constexpr int kColChunk = 256;
+// Column partial sums over row chunks of col_chunk(n) rows: short chunks for
+// small n, so the launch still has enough workgroups (at n = 256 one chunk of
+// 256 rows was a single workgroup walking every row: 26 us of a 0.45 ms
+// inversion).
+__host__ __device__ inline int64_t col_chunk(int64_t n) {
+  return n < 1024 ? 16 : n < 4096 ? 64 : 256;
+}
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) col_abs_sums(const T* A, int64_t lda, int64_t n,
                                                     double* colpart) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.y * kColChunk;
+  const int64_t chunk = col_chunk(n);
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
   if (c >= n) return;
-  const int64_t r1 = (r0 + kColChunk < n) ? r0 + kColChunk : n;
+  const int64_t r1 = (r0 + chunk < n) ? r0 + chunk : n;
   double s = 0.0;
   for (int64_t r = r0; r < r1; ++r) s += absval<T, CPLX>(A, r * lda + c);
   colpart[(int64_t)blockIdx.y * n + c] = s;
@@ -293,7 +299,7 @@ hipError_t den_transpose_t(const void* A, int64_t lda, int64_t n, double* part, 
   const T* a = static_cast<const T*>(A);
   double* rowsum = part;
   double* colpart = part + n;
-  const int nchunks = (int)((n + kColChunk - 1) / kColChunk);
+  const int nchunks = (int)((n + col_chunk(n) - 1) / col_chunk(n));
   hipLaunchKernelGGL((row_abs_sums<T, CPLX>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, a,
                      lda, n, rowsum);
   hipLaunchKernelGGL((col_abs_sums<T, CPLX>), dim3((unsigned)((n + 255) / 256), nchunks),
@@ -305,7 +311,7 @@ hipError_t den_transpose_t(const void* A, int64_t lda, int64_t n, double* part, 
 }  // namespace
 
 size_t den_partials_elems(int64_t n) {
-  return (size_t)n + (size_t)((n + kColChunk - 1) / kColChunk) * (size_t)n;
+  return (size_t)n + (size_t)((n + col_chunk(n) - 1) / col_chunk(n)) * (size_t)n;
 }
 
 hipError_t launch_den_transpose(nn_dtype dt, const void* A, int64_t lda, int64_t n, double* part,

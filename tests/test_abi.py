@@ -121,16 +121,16 @@ def test_noalloc_scratch_limits():
     nn = _nn()
     L = nn.NN_NOALLOC_SCRATCH_BYTES
     assert L == 32 << 20
-    stated = {nn.NN_F64: (1441, 1178, 1021), nn.NN_C64: (1441, 1178, 1021),
-              nn.NN_F32: (2031, 1662, 1441), nn.NN_C128: (1021, 834, 722)}
+    stated = {nn.NN_F64: (1437, 1176, 1013), nn.NN_C64: (1437, 1176, 1013),
+              nn.NN_F32: (2019, 1656, 1437), nn.NN_C128: (1013, 830, 720)}
     for dt, ns in stated.items():
         for d, n in zip((1, 2, 3), ns):
             p = nn.make_params(depth=d)
             assert 0 < nn.nn_workspace_size(n, dt, ctypes.byref(p)) <= L
             assert nn.nn_workspace_size(n + 1, dt, ctypes.byref(p)) > L
     p = nn.make_params(depth=2, prec="mixed", x0="identity")
-    assert 0 < nn.nn_workspace_size(700, nn.NN_F64, ctypes.byref(p)) <= L
-    assert nn.nn_workspace_size(701, nn.NN_F64, ctypes.byref(p)) > L
+    assert 0 < nn.nn_workspace_size(698, nn.NN_F64, ctypes.byref(p)) <= L
+    assert nn.nn_workspace_size(699, nn.NN_F64, ctypes.byref(p)) > L
 
 
 def test_cns_argument_errors_and_workspace():
