@@ -13,12 +13,10 @@
 //  * persistent kernel: each workgroup pops work items from the counter
 //    until the queue is empty (every wave reaches that exit).  A matrix's
 //    iterate and residual live in LDS for all its nests (buffers X and R, plus
-//    U for depth >= 3); G is staged from global memory (L2 after the first
-//    read) into R's buffer before each residual, which the product then
-//    overwrites, and U = R + R R overwrites R at depth 2.  Two buffers instead
-//    of four halve the LDS of a K = 64 complex matrix to 68 KB, and the
-//    register budget is held to 256 per lane, so two workgroups — two waves
-//    per SIMD — share a CU.
+//    U for depth >= 3); the residual reads G straight from global memory (L2
+//    after the first read), and U = R + R R overwrites R at depth 2.  Two
+//    buffers instead of four halve the LDS of a K = 64 complex matrix to
+//    68 KB, so two workgroups share a CU.
 //  * every product is an LDS-to-register GEMM on v_mfma_f32_16x16x4_f32; a
 //    complex product is the real product of the interleaved left factor with
 //    the real 2K x 2K form of the right factor, expanded on read (row 2k is
@@ -45,7 +43,8 @@ constexpr int kMaxN = 64;
 // Eight waves per workgroup: a "group" matrix is shared by all eight (a K = 64
 // complex product is 32 output blocks, 4 per wave), a "wave" item holds
 // eight matrices of one wave each.
-constexpr int kStageBatch = 8;  // global loads in flight per thread when staging G
+constexpr int kStageBatch = 4;  // global loads in flight per thread when staging G
+constexpr int kDenLanes = 4;    // lanes per row or column sum of the transpose start
 constexpr int kThreads = 512;
 constexpr int kWaves = 8;
 constexpr int kMaxBlocks = 8;  // 16x16 output blocks per wave
@@ -74,11 +73,11 @@ __device__ __host__ __forceinline__ int lds_buf(int K, bool cplx) {
 
 // Column swizzle of complex rows: when a row's padded width is a multiple of
 // 32 floats, rows 2 and 3 mod 4 store column c at c ^ 16.  With ld = 4 mod 32
-// the B-fragment reads of a k-group (8-byte pairs of complex rows 2 lk and
-// 2 lk + 1 for lane quarter lk, 32 lanes at a time) otherwise put lane
-// quarters 0 and 1 on overlapping banks (row offset 2 ld = 8 mod 64); the
-// swizzle moves one of them 16 banks away.  16-byte segments stay whole (bit
-// 4 only) and the A-fragment reads stay conflict free.  swz: 0 or 16.
+// the B-fragment reads of a k-group (complex rows 2 lk and 2 lk + 1 for lane
+// quarter lk) otherwise put lane quarters 0 and 1 on overlapping banks (row
+// offset 2 ld = 8 mod 64); the swizzle moves one of them 16 banks away.
+// 16-byte segments stay whole (bit 4 only) and the A-fragment reads stay
+// conflict free.  swz: 0 or 16.
 __device__ __host__ __forceinline__ int lds_swz(int K, bool cplx) {
   return cplx && (pad16(2 * K) & 31) == 0 ? 16 : 0;
 }
@@ -121,22 +120,23 @@ typedef float f2_t __attribute__((ext_vector_type(2)));
 template <bool CPLX, int NB, bool SH>
 struct KFrag {
   f4_t a[SH ? 1 : NB];
-  f4_t b[NB];  // complex: (p0.x, p0.y, p1.x, p1.y); real: 4 rows of B
+  f4_t b[NB];  // complex: this lane's column of two complex rows (x, y); real: 4 rows
 };
 
-template <bool CPLX, int NB, bool SH>
+template <bool CPLX, int NB, bool SH, bool WITH_A = true>
 __device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB, SH>& f, const int* aoff,
                                             const int* boff, int j, int ld, int sa) {
+  if constexpr (WITH_A) {
 #pragma unroll
-  for (int i = 0; i < (SH ? 1 : NB); ++i)
-    f.a[i] = *reinterpret_cast<const f4_t*>(&smem[aoff[i] + ((16 * j) ^ sa)]);
+    for (int i = 0; i < (SH ? 1 : NB); ++i)
+      f.a[i] = *static_cast<const f4_t*>(
+          __builtin_assume_aligned(&smem[aoff[i] + ((16 * j) ^ sa)], 16));
+  }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if constexpr (CPLX) {
       const int o = boff[i] + 8 * j * ld;
-      const f2_t p0 = *reinterpret_cast<const f2_t*>(&smem[o]);
-      const f2_t p1 = *reinterpret_cast<const f2_t*>(&smem[o + ld]);
-      f.b[i] = f4_t{p0.x, p0.y, p1.x, p1.y};
+      f.b[i] = f4_t{smem[o], smem[o + ld], 0.f, 0.f};
     } else {
       const int o = boff[i] + 16 * j * ld;
       f.b[i] = f4_t{smem[o], smem[o + ld], smem[o + 2 * ld], smem[o + 3 * ld]};
@@ -147,19 +147,26 @@ __device__ __forceinline__ void load_kgroup(KFrag<CPLX, NB, SH>& f, const int* a
 // The four MFMA steps of a k-group, step-major over the blocks: consecutive
 // MFMAs write different accumulators, so one does not wait for the previous
 // one's result (each accumulator still sums its k in the same order).
+// The value lane n ^ 1 holds (adjacent lanes swap: DPP quad_perm 1,0,3,2).
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
 template <bool CPLX, int NB, bool SH>
 __device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB, SH>& f,
-                                           const bool* even) {
+                                           const int* sgn) {
   float b[NB][4];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if constexpr (CPLX) {
-      // expanded rows 2 kc, 2 kc + 1 of two complex rows kc0, kc0 + 1
-      const bool ev = even[i];
-      b[i][0] = ev ? f.b[i].x : f.b[i].y;
-      b[i][1] = ev ? -f.b[i].y : f.b[i].x;
-      b[i][2] = ev ? f.b[i].z : f.b[i].w;
-      b[i][3] = ev ? -f.b[i].w : f.b[i].z;
+      // expanded rows 2 kc and 2 kc + 1 of the complex rows kc0, kc0 + 1 at
+      // this lane's real column n: row 2 kc is B[kc][n] as stored; row 2 kc + 1
+      // is -B[kc][n + 1] for even n (-im) and B[kc][n - 1] for odd n (re),
+      // i.e. the partner lane's value with the sign bit flipped on even lanes
+      b[i][0] = f.b[i].x;
+      b[i][1] = __int_as_float(__float_as_int(pair_swap(f.b[i].x)) ^ sgn[i]);
+      b[i][2] = f.b[i].y;
+      b[i][3] = __int_as_float(__float_as_int(pair_swap(f.b[i].y)) ^ sgn[i]);
     } else {
       b[i][0] = f.b[i].x;
       b[i][1] = f.b[i].y;
@@ -184,16 +191,24 @@ __device__ __forceinline__ void mma_kgroup(f4_t* acc, const KFrag<CPLX, NB, SH>&
 // k-assignment: in k-group j (16 real k) MFMA step q takes, for the lanes of
 // quarter lk, k = 16 j + 4 lk + q.  Each step still covers four distinct k, and
 // a lane's four A values of the group are contiguous (one 16-byte read).  For
-// a complex B the four k are the rows 2 kc, 2 kc + 1 of two complex rows, whose
-// expanded entries come from one 8-byte (re, im) read each.  All operand reads
+// a complex B the four k are the rows 2 kc, 2 kc + 1 of two complex rows: a
+// lane reads its own column of each complex row and takes the other half of
+// the (re, im) pair from the adjacent lane (DPP), so the expansion costs two
+// 4-byte reads and two lane swaps per block and k-group.  All operand reads
 // of a k-group are issued before its MFMAs; when a wave's blocks share a block
 // row (SH) their A fragment is read once.  (Reading k-group j + 1 during the
 // MFMAs of k-group j needs a second register set, which made the compiler
 // spill in this fully inlined kernel.)
-template <bool CPLX, int NB, bool SH>
+//
+// GA: the left factor is read from global memory instead of LDS (Ag, row-major
+// K x cols floats); the residual R = I - G X reads G this way, so G is staged
+// into LDS only once, for the transpose start, not before every residual.  A lane's fragment of k-group j + 1 is loaded while the MFMAs of
+// k-group j run (L2 latency hidden by one k-group); out-of-range fragments
+// read as zero, as the LDS padding does, so both forms give the same bits.
+template <bool CPLX, int NB, bool SH, bool GA = false>
 __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, int ld,
                                             float alpha, float diag, const Group& g,
-                                            double* ss, int swz) {
+                                            double* ss, int swz, const float* Ag = nullptr) {
   const int cols = CPLX ? 2 * K : K;
   const int nbm = (K + 15) >> 4, nbn = (cols + 15) >> 4, nb = nbm * nbn;
   const int first = g.gw * NB;
@@ -202,8 +217,8 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
   // and + 1): fixed per lane
   const int sa = ((lr >> 1) & 1) * swz, sb = (lk & 1) * swz;
   f4_t acc[NB];
-  int aoff[NB], boff[NB], bm_[NB], bn_[NB];
-  bool even[NB], live[NB];
+  int aoff[NB], boff[NB], bm_[NB], bn_[NB], sgn[NB];
+  bool live[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     acc[i] = f4_t{};
@@ -214,20 +229,73 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
     const int n = bn_[i] * 16 + lr;
     aoff[i] = A + (bm_[i] * 16 + lr) * ld + 4 * lk;
     if constexpr (CPLX) {
-      boff[i] = B + (2 * lk) * ld + ((n & ~1) ^ sb);
-      even[i] = !(n & 1);
+      boff[i] = B + (2 * lk) * ld + (n ^ sb);
+      sgn[i] = (n & 1) ? 0 : (int)0x80000000u;
     } else {
       boff[i] = B + (4 * lk) * ld + n;
-      even[i] = true;
+      sgn[i] = 0;
     }
   }
   const int kgroups = nbn;  // padded real inner dimension / 16
-  for (int j = 0; j < kgroups; ++j) {
-    KFrag<CPLX, NB, SH> f;
-    load_kgroup<CPLX, NB, SH>(f, aoff, boff, j, ld, sa);  // all operand reads of the group first
-    mma_kgroup<CPLX, NB, SH>(acc, f, even);
+  if constexpr (GA) {
+    constexpr int NA = SH ? 1 : NB;
+    const float* arow[NA];
+    bool aok[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int m = bm_[i] * 16 + lr;
+      aok[i] = m < K;
+      arow[i] = Ag + (aok[i] ? m : 0) * cols + 4 * lk;
+    }
+    // 16-byte loads when every row starts 16-byte aligned, else four 4-byte
+    // loads (uniform choice)
+    const bool vec = (reinterpret_cast<uintptr_t>(Ag) & 15) == 0 && (cols & 3) == 0;
+    auto gload = [&](int j, f4_t* dst) {
+      const int c = 16 * j + 4 * lk;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        if (vec) {
+          dst[i] = aok[i] && c < cols ? *reinterpret_cast<const f4_t*>(arow[i] + 16 * j)
+                                      : f4_t{};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dst[i][e] = aok[i] && c + e < cols ? arow[i][16 * j + e] : 0.f;
+        }
+      }
+    };
+    f4_t an[NA];
+    gload(0, an);
+    for (int j = 0; j < kgroups; ++j) {
+      KFrag<CPLX, NB, SH> f;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) f.a[i] = an[i];
+      if (j + 1 < kgroups) gload(j + 1, an);
+      load_kgroup<CPLX, NB, SH, false>(f, aoff, boff, j, ld, sa);  // B only
+      mma_kgroup<CPLX, NB, SH>(acc, f, sgn);
+    }
+  } else {
+    for (int j = 0; j < kgroups; ++j) {
+      KFrag<CPLX, NB, SH> f;
+      load_kgroup<CPLX, NB, SH>(f, aoff, boff, j, ld, sa);  // all operand reads of the group first
+      mma_kgroup<CPLX, NB, SH>(acc, f, sgn);
+    }
   }
   // Epilogue in registers (rows 4 (lane/16) + t of each block, FP32 layout).
+  // Every E read is issued before the first use.  Entries outside a ragged
+  // matrix lie in the zero padding of the buffers and are set to zero here, so
+  // the padding stays zero and the stores need no per-element test.
+  float ev[NB][4];
+  if (E >= 0) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int n = bn_[i] * 16 + lr;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int m = bm_[i] * 16 + 4 * lk + t;
+        ev[i][t] = smem[E + m * ld + scol(m, n, swz)];
+      }
+    }
+  }
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -235,23 +303,25 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int m = bm_[i] * 16 + 4 * lk + t;
-      if (live[i] && m < K && n < cols) {
-        float v = alpha * acc[i][t];
-        if (E >= 0) v += smem[E + m * ld + scol(m, n, swz)];
-        if (CPLX ? (n == 2 * m) : (n == m)) v += diag;
-        acc[i][t] = v;
-        s += (double)v * (double)v;
-      }
+      float v = alpha * acc[i][t];
+      if (E >= 0) v += ev[i][t];
+      if (CPLX ? (n == 2 * m) : (n == m)) v += diag;
+      v = m < K && n < cols ? v : 0.f;
+      acc[i][t] = v;
+      if (ss && live[i]) s += (double)v * (double)v;
     }
   }
-  g.sync();  // every read of A, B, E is done
+  // every read of A, B, E is done before C (which may alias them) is written;
+  // the residual's C aliases none of its LDS inputs
+  if (C == B || C == E || (!GA && C == A)) g.sync();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
+    if (!live[i]) continue;  // a recomputed copy of another wave's block
     const int n = bn_[i] * 16 + lr;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int m = bm_[i] * 16 + 4 * lk + t;
-      if (live[i] && m < K && n < cols) smem[C + m * ld + scol(m, n, swz)] = acc[i][t];
+      smem[C + m * ld + scol(m, n, swz)] = acc[i][t];
     }
   }
   if (ss) {
@@ -350,40 +420,56 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     for (int r = g.gw; r < K; r += g.G)
       for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + scol(r, c, swz)];
   };
-  stage_g();
+  // The residual reads G from global memory (L2 after the first read); the
+  // transpose start reads it from LDS, staged into R's buffer.
+  if (x0 == NN_X0_TRANSPOSE) stage_g();
   // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G;
   // NN_X0_GIVEN reads X_0 from Xg.
   double den = 1.0;
   if (x0 == NN_X0_TRANSPOSE) {
-    if (g.gtid < 2 * K) {
-      const bool row = g.gtid < K;
-      const int i = row ? g.gtid : g.gtid - K;
+    // 2K sums of K moduli (rows 0..K-1, then columns), each split over
+    // kDenLanes adjacent lanes (element j to lane j mod kDenLanes, then a
+    // shuffle tree): the order depends on K only, not on the group size, so a
+    // matrix gets the same den on the one-wave and the whole-group path.
+    const int per_pass = nthr / kDenLanes;
+    for (int base = 0; base < 2 * K; base += per_pass) {
+      const int sidx = base + g.gtid / kDenLanes, part = g.gtid % kDenLanes;
       double s = 0.0;
-      for (int j = 0; j < K; ++j) {
-        const int r = row ? i : j, c = row ? j : i;
-        if constexpr (CPLX) {
-          const double re = smem[Gs + r * ld + scol(r, 2 * c, swz)];
-          const double im = smem[Gs + r * ld + scol(r, 2 * c + 1, swz)];
-          s += sqrt(re * re + im * im);
-        } else {
-          s += fabs((double)smem[Gs + r * ld + c]);
+      if (sidx < 2 * K) {
+        const bool row = sidx < K;
+        const int i = row ? sidx : sidx - K;
+        for (int j = part; j < K; j += kDenLanes) {
+          const int r = row ? i : j, c = row ? j : i;
+          if constexpr (CPLX) {
+            const double re = smem[Gs + r * ld + scol(r, 2 * c, swz)];
+            const double im = smem[Gs + r * ld + scol(r, 2 * c + 1, swz)];
+            s += sqrt(re * re + im * im);
+          } else {
+            s += fabs((double)smem[Gs + r * ld + c]);
+          }
         }
       }
-      red[8 + g.gtid] = s;
+#pragma unroll
+      for (int o = kDenLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (sidx < 2 * K && part == 0) red[8 + sidx] = s;
     }
     g.sync();
-    double n1 = 0.0, ninf = 0.0;
-    bool bad = false;
-    for (int i = 0; i < K; ++i) {
-      const double r = red[8 + i], c = red[8 + K + i];
-      bad |= !isfinite(r) || !isfinite(c);
-      ninf = r > ninf ? r : ninf;
-      n1 = c > n1 ? c : n1;
+    // ||G||_inf = max over rows, ||G||_1 = max over columns: lane l takes row
+    // and column l (K <= 64), then a wave maximum (every wave the same)
+    const int l = g.lane;
+    double ninf = l < K ? red[8 + l] : 0.0, n1 = l < K ? red[8 + K + l] : 0.0;
+    int bad = !isfinite(ninf) || !isfinite(n1);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double a = __shfl_xor(ninf, o, 64), b = __shfl_xor(n1, o, 64);
+      ninf = a > ninf ? a : ninf;
+      n1 = b > n1 ? b : n1;
+      bad |= __shfl_xor(bad, o, 64);
     }
     den = bad ? NAN : n1 * ninf;
   } else if (x0 == NN_X0_SCALED_IDENTITY) {
     double t = 0.0;
-    for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + scol(i, CPLX ? 2 * i : i, swz)];
+    for (int i = 0; i < K; ++i) t += (double)Ag[i * cols + (CPLX ? 2 * i : i)];
     den = t;
   }
   const bool den_ok = isfinite(den) && den > 0.0;
@@ -419,10 +505,10 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     status = isfinite(den) ? NN_ERR_DIVERGED : NN_ERR_NONFINITE;
   } else {
     for (;;) {
-      if (k > 0) stage_g();  // the first residual finds G staged by the start
       double ss = 0.0;
       const bool want = !fixed || k == iters;
-      lds_gemm_nb<CPLX, NB, SH>(Gs, Xs, -1, Rs, K, ld, -1.f, 1.f, g, want ? &ss : nullptr, swz);  // R = I - G X
+      lds_gemm_nb<CPLX, NB, SH, true>(-1, Xs, -1, Rs, K, ld, -1.f, 1.f, g, want ? &ss : nullptr,
+                                      swz, Ag);  // R = I - G X
       if (fixed) {
         if (k == iters) {
           rms = sqrt(ss / (double)K);
