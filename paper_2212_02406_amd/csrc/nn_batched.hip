@@ -43,7 +43,7 @@ constexpr int kMaxN = 64;
 // Eight waves per workgroup: a "group" matrix is shared by all eight (a K = 64
 // complex product is 32 output blocks, 4 per wave), a "wave" item holds
 // eight matrices of one wave each.
-constexpr int kStageBatch = 4;  // global loads in flight per thread when staging G
+constexpr int kStageBatch = 16;  // global loads in flight per thread when staging G
 constexpr int kDenLanes = 4;    // lanes per row or column sum of the transpose start
 constexpr int kThreads = 512;
 constexpr int kWaves = 8;
@@ -385,16 +385,16 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       for (int e = g.gtid; e < nb; e += nthr) smem[buf + q * bufstride + e] = 0.f;
     g.sync();
   }
-  // G (row-major, K x cols floats) into R's buffer: waves over rows, lanes
-  // over columns (coalesced, no index division)
-  // The group's threads take consecutive elements of the row-major K x cols
-  // matrix (coalesced) and issue kStageBatch loads before storing any, so a
-  // staging costs about one memory round trip per batch: with one load and
-  // store per row and column step, each store waited for its own load (16
-  // round trips per thread for K = 64 complex; the restaging of G was 11-14%
-  // of the 4096-matrix batch).
+  // Staging of a row-major K x cols matrix into an LDS buffer: the group's
+  // threads take consecutive elements (coalesced) and issue kStageBatch loads
+  // before storing any, so a K = 64 complex matrix costs one memory round
+  // trip per thread instead of one per element.  A thread's element
+  // e = r cols + c advances by nthr = dr cols + dc per load, so (r, c) is
+  // carried along without a division per element.
   auto stage = [&](int dst, const float* src) {
     const int tot = K * cols;
+    const int dr = nthr / cols, dc = nthr - dr * cols;
+    int r = g.gtid / cols, c = g.gtid - r * cols;
     for (int e0 = g.gtid; e0 < tot; e0 += kStageBatch * nthr) {
       float v[kStageBatch];
 #pragma unroll
@@ -404,10 +404,12 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
       }
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
-        const int e = e0 + u * nthr;
-        if (e < tot) {
-          const int r = e / cols, c = e - r * cols;
-          smem[dst + r * ld + scol(r, c, swz)] = v[u];
+        if (e0 + u * nthr < tot) smem[dst + r * ld + scol(r, c, swz)] = v[u];
+        c += dc;
+        r += dr;
+        if (c >= cols) {
+          c -= cols;
+          ++r;
         }
       }
     }
@@ -420,9 +422,10 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     for (int r = g.gw; r < K; r += g.G)
       for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + scol(r, c, swz)];
   };
-  // The residual reads G from global memory (L2 after the first read); the
-  // transpose start reads it from LDS, staged into R's buffer.
-  if (x0 == NN_X0_TRANSPOSE) stage_g();
+  // G is staged into R's buffer once, with all of a thread's loads in flight:
+  // the start reads it there, and the staging brings G into L2, where every
+  // residual then reads it.
+  stage_g();
   // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G;
   // NN_X0_GIVEN reads X_0 from Xg.
   double den = 1.0;
@@ -469,7 +472,7 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     den = bad ? NAN : n1 * ninf;
   } else if (x0 == NN_X0_SCALED_IDENTITY) {
     double t = 0.0;
-    for (int i = 0; i < K; ++i) t += (double)Ag[i * cols + (CPLX ? 2 * i : i)];
+    for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + scol(i, CPLX ? 2 * i : i, swz)];
     den = t;
   }
   const bool den_ok = isfinite(den) && den > 0.0;
@@ -478,21 +481,22 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   if (x0 == NN_X0_GIVEN) {
     stage(Xs, Xg);
   } else {
-    for (int e = g.gtid; e < K * cols; e += nthr) {
-      const int r = e / cols, c = e - r * cols;
-      float v;
-      if (x0 == NN_X0_TRANSPOSE) {
-        if constexpr (CPLX) {
-          const int j = c >> 1;  // X[r][j] = conj(G[j][r]) * s
-          v = (c & 1) ? -smem[Gs + j * ld + scol(j, 2 * r + 1, swz)] * s
-                      : smem[Gs + j * ld + scol(j, 2 * r, swz)] * s;
+    for (int r = g.gw; r < K; r += g.G) {
+      for (int c = g.lane; c < cols; c += 64) {
+        float v;
+        if (x0 == NN_X0_TRANSPOSE) {
+          if constexpr (CPLX) {
+            const int j = c >> 1;  // X[r][j] = conj(G[j][r]) * s
+            v = (c & 1) ? -smem[Gs + j * ld + scol(j, 2 * r + 1, swz)] * s
+                        : smem[Gs + j * ld + scol(j, 2 * r, swz)] * s;
+          } else {
+            v = smem[Gs + c * ld + r] * s;
+          }
         } else {
-          v = smem[Gs + c * ld + r] * s;
+          v = (CPLX ? (c == 2 * r) : (c == r)) ? s : 0.f;
         }
-      } else {
-        v = (CPLX ? (c == 2 * r) : (c == r)) ? s : 0.f;
+        smem[Xs + r * ld + scol(r, c, swz)] = v;
       }
-      smem[Xs + r * ld + scol(r, c, swz)] = v;
     }
   }
   g.sync();
