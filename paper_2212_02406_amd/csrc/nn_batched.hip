@@ -635,7 +635,12 @@ template <bool CPLX, bool TOL, int MAXNB>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
   __shared__ int item_s;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // Values that are the same for a whole wave (the work item, the matrix and
+  // its size) are read through readfirstlane, so the compiler keeps them and
+  // everything derived from them (strides, block counts, loop bounds) in
+  // scalar registers and runs the k-loops as uniform loops.
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int cm = CPLX ? 2 : 1;
   const float* A = static_cast<const float*>(a.A);
   float* X = static_cast<float*>(a.X);
@@ -647,14 +652,14 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
   for (;;) {
     if (tid == 0) item_s = atomicAdd(&hdr->counter, 1);
     __syncthreads();
-    const int item = item_s;
+    const int item = __builtin_amdgcn_readfirstlane(item_s);
     __syncthreads();
     if (item >= n_items) break;
     if (item < n_large) {
-      const int b = perm[item];
+      const int b = __builtin_amdgcn_readfirstlane(perm[item]);
       const Group g{wave, kWaves, lane, tid, 0, true};
       const int64_t off = a.offsets[b] * cm, xoff = xoffsets[b] * cm;
-      const int K = a.sizes[b];
+      const int K = __builtin_amdgcn_readfirstlane(a.sizes[b]);
       const double tol = a.tols ? a.tols[b] : a.tol;
       const int mit = a.maxits ? a.maxits[b] : a.max_iter;
       nn_info_dev* inf = a.info ? a.info + b : nullptr;
@@ -683,10 +688,10 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
     } else {
       const int idx = n_large + kWaves * (item - n_large) + wave;
       if (idx < n_large + n_small) {
-        const int b = perm[idx];
+        const int b = __builtin_amdgcn_readfirstlane(perm[idx]);
         const Group g{0, 1, lane, lane, wave, false};
         const int64_t off = a.offsets[b] * cm, xoff = xoffsets[b] * cm;
-        const int K = a.sizes[b];
+        const int K = __builtin_amdgcn_readfirstlane(a.sizes[b]);
         const double tol = a.tols ? a.tols[b] : a.tol;
         const int mit = a.maxits ? a.maxits[b] : a.max_iter;
         const int base = wave * lds_nbufs(a.depth) * wave_stride;
