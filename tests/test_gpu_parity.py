@@ -44,6 +44,13 @@ def _relF(X, Y):
     return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
 
 
+def _relmax(X, Y):
+    """Largest entrywise difference relative to the largest entry of Y: a
+    wrong tile or block of X shows here at its own size, where the Frobenius
+    norm of the whole matrix would dilute it."""
+    return float(np.abs(X - Y).max() / np.abs(Y).max())
+
+
 def _to_dev(A, ld=None):
     """Upload A; with ld > n the matrix is a view with leading dimension ld."""
     n = A.shape[0]
@@ -91,6 +98,7 @@ def test_config1_n256_fp64(d, x0):
     # forced identical k: strict parity, and the traces agree nest by nest
     X, info = _gpu_invert(A, depth=d, x0=x0, fixed_iter=io["iters"])
     assert _relF(X, Xo) < 1e-10
+    assert _relmax(X, Xo) < 1e-10
     tr = info["trace"]
     for a, b in zip(tr, io["trace"]):
         assert abs(a - b) <= 1e-9 * b + 1e-14
@@ -107,6 +115,7 @@ def test_ragged_sizes_fp64(n, ld):
     X, info = _gpu_invert(A, ld=ld, depth=2, fixed_iter=6)
     assert info["status"] == nn.NN_OK
     assert _relF(X, Xo) < 1e-10
+    assert _relmax(X, Xo) < 1e-10
     assert abs(info["rms"] - io["rms"]) <= 1e-9 * io["rms"] + 1e-15
 
 
@@ -133,6 +142,7 @@ def test_every_tile_config(tile, dtype, n, monkeypatch):
         single = np.dtype(dtype) in (np.dtype(np.float32), np.dtype(np.complex64))
         tol = 64 * U32 * np.linalg.cond(ref) if single else 1e-10
         assert _relF(X.astype(ref.dtype), Xo) < tol
+        assert _relmax(X.astype(ref.dtype), Xo) < tol
 
 
 @pytest.mark.parametrize("n", [5, 64, 130, 300])
@@ -143,6 +153,7 @@ def test_nonsymmetric_fp64(n):
     Xo, io = oracle.nn_ref(A, d=2, fixed_iter=8)
     X, info = _gpu_invert(A, depth=2, fixed_iter=8)
     assert _relF(X, Xo) < 1e-10
+    assert _relmax(X, Xo) < 1e-10
 
 
 @pytest.mark.parametrize("n,ld", [(16, 16), (100, 101), (256, 256), (390, 390)])
@@ -156,6 +167,7 @@ def test_fp32(n, ld, d):
     X, info = _gpu_invert(A32, ld=ld, depth=d, fixed_iter=12 if d == 2 else 18)
     assert info["status"] == nn.NN_OK
     assert _relF(X.astype(np.float64), Xo) < 64 * U32 * kappa
+    assert _relmax(X.astype(np.float64), Xo) < 64 * U32 * kappa
 
 
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
@@ -170,6 +182,7 @@ def test_complex(dtype, n):
     X, info = _gpu_invert(A, depth=2, fixed_iter=10)
     tol = 1e-10 if dtype == np.complex128 else 64 * U32 * np.linalg.cond(A128)
     assert _relF(X.astype(np.complex128), Xo) < tol
+    assert _relmax(X.astype(np.complex128), Xo) < tol
 
 
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
@@ -181,6 +194,7 @@ def test_complex_hpd_identity_start(dtype):
     X, info = _gpu_invert(A, depth=3, x0="identity", fixed_iter=6)
     tol = 1e-10 if dtype == np.complex128 else 64 * U32 * np.linalg.cond(A128)
     assert _relF(X.astype(np.complex128), Xo) < tol
+    assert _relmax(X.astype(np.complex128), Xo) < tol
 
 
 def test_restart_from_given_iterate():
