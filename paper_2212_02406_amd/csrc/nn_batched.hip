@@ -6,10 +6,12 @@
 // (K <= 64), a fixed number of nests at depth d (Sec. II-D Theorem).
 //
 // Structure:
-//  * plan kernel (one block): counting sort of the matrices by size, largest
-//    first (longest-processing-time order), the split into "group" matrices
-//    (a whole 8-wave workgroup each) and "wave" matrices (K <= wave_max_k,
-//    one wave each, eight per work item), and the reset of the work counter.
+//  * plan kernel (one block): stable counting sort of the matrices by size,
+//    largest first (longest-processing-time order), the split into "group"
+//    matrices (a whole 8-wave workgroup each), "pairs" (fixed-nest mode, K up
+//    to 32: two matrices of one size per workgroup, four waves each) and
+//    "wave" matrices (K <= wave_max_k, one wave each, eight per work item),
+//    and the reset of the work counter.
 //  * persistent kernel: each workgroup pops work items from the counter
 //    until the queue is empty (every wave reaches that exit).  A matrix's
 //    iterate and residual live in LDS for all its nests (buffers X and R, plus
@@ -48,6 +50,12 @@ constexpr int kDenLanes = 4;    // lanes per row or column sum of the transpose 
 constexpr int kThreads = 512;
 constexpr int kWaves = 8;
 constexpr int kMaxBlocks = 8;  // 16x16 output blocks per wave
+// Fixed-nest matrices of K in (wave_max_k, kQuadMaxK] run in pairs, four
+// waves each, so that a workgroup's eight waves carry two blocks each instead
+// of one: the two matrices of a pair have the same size and control flow and
+// meet the same workgroup barriers.
+constexpr int kQuadWaves = 4;
+constexpr int kQuadMaxK = 32;
 
 struct BatchHdr {
   int32_t counter;
@@ -55,7 +63,8 @@ struct BatchHdr {
   int32_t n_small;
   int32_t n_items;
   int32_t bad;
-  int32_t pad[3];
+  int32_t n_quad;  // matrices in pairs (an even count)
+  int32_t pad[2];
 };
 
 // LDS layout of a K x K matrix: real columns padded to a multiple of 16 plus
@@ -296,10 +305,11 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
       }
     }
   }
-  double s = 0.0;
+  double ssq[NB];  // this lane's part of each block's sum of squares
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int n = bn_[i] * 16 + lr;
+    ssq[i] = 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int m = bm_[i] * 16 + 4 * lk + t;
@@ -308,7 +318,7 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
       if (CPLX ? (n == 2 * m) : (n == m)) v += diag;
       v = m < K && n < cols ? v : 0.f;
       acc[i][t] = v;
-      if (ss && live[i]) s += (double)v * (double)v;
+      if (ss) ssq[i] += (double)v * (double)v;
     }
   }
   // every read of A, B, E is done before C (which may alias them) is written;
@@ -325,15 +335,21 @@ __device__ __forceinline__ void lds_gemm_nb(int A, int B, int E, int C, int K, i
     }
   }
   if (ss) {
-    s = wave_sum(s);
-    if (g.G > 1) {
-      if (g.lane == 0) s_red[g.redrow][g.gw] = s;
-      g.sync();
-      double t = 0.0;
-      for (int w = 0; w < g.G; ++w) t += s_red[g.redrow][w];
-      s = t;
+    // Each block's sum (a butterfly over the lanes), then the blocks in block
+    // order: the same association whichever waves hold the blocks, so a
+    // matrix's rms has the same bits on the whole-group, paired and one-wave
+    // paths (and in both control modes).
+#pragma unroll
+    for (int i = 0; i < NB; ++i) ssq[i] = wave_sum(ssq[i]);
+    if (g.lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (live[i]) s_red[g.redrow][first + i] = ssq[i];
     }
-    *ss = s;
+    g.sync();
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += s_red[g.redrow][b];
+    *ss = t;
   }
   g.sync();
 }
@@ -383,8 +399,10 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     const int nb = lds_buf(K, CPLX);
     for (int q = 0; q < lds_nbufs(depth); ++q)
       for (int e = g.gtid; e < nb; e += nthr) smem[buf + q * bufstride + e] = 0.f;
-    g.sync();
   }
+  // unconditional, so that how many barriers a matrix meets does not depend on
+  // its size (the two matrices of a pair share the workgroup barriers)
+  g.sync();
   // Staging of a row-major K x cols matrix into an LDS buffer: the group's
   // threads take consecutive elements (coalesced) and issue kStageBatch loads
   // before storing any, so a K = 64 complex matrix costs one memory round
@@ -563,55 +581,131 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
   g.sync();
 }
 
+// Plan of one launch: a stable counting sort of the matrices by size, largest
+// first (longest-processing-time order), into four regions of perm:
+//   large  K > quad_max_k, one matrix per 8-wave item, then one matrix of each
+//          quad-class size with an odd count (also run as a whole item);
+//   quad   wave_max_k < K <= quad_max_k, pairs of equal size, one pair per
+//          item (four waves each);
+//   small  K <= wave_max_k, eight matrices per item (one wave each);
+// then the entries with an invalid size (reported, never run).  Within a size
+// the order is the batch order: each wave ranks its lanes by ballots and the
+// waves' counts are prefix-summed, so the plan is the same on every run.
 __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int batch, int max_n,
-                                                     int wave_max_k, BatchHdr* hdr, int32_t* perm,
+                                                     int wave_max_k, int quad_max_k,
+                                                     BatchHdr* hdr, int32_t* perm,
                                                      nn_info_dev* info) {
-  __shared__ int cnt[kMaxN + 1], start[kMaxN + 1], fill[kMaxN + 1];
+  constexpr int NW = 1024 / 64;
+  __shared__ int cnt[kMaxN + 1], start[kMaxN + 1], left[kMaxN + 1], coff[kMaxN + 1],
+      ctot[kMaxN + 1];
+  __shared__ int wcnt[NW][kMaxN + 1];
   __shared__ int bad;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   if (t <= kMaxN) {
     cnt[t] = 0;
-    fill[t] = 0;
+    coff[t] = 0;
   }
+  for (int e = t; e < NW * (kMaxN + 1); e += 1024) (&wcnt[0][0])[e] = 0;
   if (t == 0) bad = 0;
   __syncthreads();
-  for (int b = t; b < batch; b += blockDim.x) {
-    int k = sizes[b];
-    if (k < 1 || k > max_n) {
-      k = 0;
+  // size of entry b (0: invalid, reported), -1 past the end of the batch
+  auto size_of = [&](int b) {
+    if (b >= batch) return -1;
+    const int k = sizes[b];
+    return k < 1 || k > max_n ? 0 : k;
+  };
+  // this lane's rank among the lanes of its wave with the same size, and the
+  // wave's count of each size present (written by the first such lane)
+  auto rank_in_wave = [&](int k, int* counts) {
+    int rank = 0;
+    uint64_t todo = __ballot(k >= 0);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const int kk = __shfl(k, leader, 64);
+      const uint64_t m = __ballot(k == kk);
+      if (k == kk) rank = __popcll(m & ((1ull << lane) - 1));
+      if (lane == leader) counts[kk] = __popcll(m);
+      todo &= ~m;
+    }
+    return rank;
+  };
+  for (int c0 = 0; c0 < batch; c0 += 1024) {
+    const int k = size_of(c0 + t);
+    if (k == 0) {
       bad = 1;
       if (info) {
         nn_info_dev d;
         d.iters = 0;
         d.status = NN_ERR_ARG;
         d.rms = NAN;
-        info[b] = d;
+        info[c0 + t] = d;
       }
     }
-    atomicAdd(&cnt[k], 1);
+    (void)rank_in_wave(k, wcnt[w]);
+    __syncthreads();
+    if (t <= kMaxN) {
+      int run = 0;
+      for (int v = 0; v < NW; ++v) {
+        run += wcnt[v][t];
+        wcnt[v][t] = 0;
+      }
+      cnt[t] += run;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (t == 0) {
+    const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
     int acc = 0;
-    for (int k = kMaxN; k >= 1; --k) {
+    for (int k = kMaxN; k > qk; --k) {
       start[k] = acc;
       acc += cnt[k];
     }
+    for (int k = qk; k > wk; --k)
+      if (cnt[k] & 1) left[k] = acc++;
+    const int n_large = acc;
+    for (int k = qk; k > wk; --k) {
+      start[k] = acc;
+      acc += cnt[k] & ~1;
+    }
+    const int n_quad = acc - n_large;
+    for (int k = wk; k >= 1; --k) {
+      start[k] = acc;
+      acc += cnt[k];
+    }
+    const int n_small = acc - n_large - n_quad;
     start[0] = acc;
-    int large = 0;
-    for (int k = wave_max_k + 1; k <= kMaxN; ++k) large += cnt[k];
-    const int small = batch - cnt[0] - large;
     hdr->counter = 0;
-    hdr->n_large = large;
-    hdr->n_small = small;
-    hdr->n_items = large + (small + kWaves - 1) / kWaves;
+    hdr->n_large = n_large;
+    hdr->n_quad = n_quad;
+    hdr->n_small = n_small;
+    hdr->n_items = n_large + n_quad / 2 + (n_small + kWaves - 1) / kWaves;
     hdr->bad = bad;
   }
   __syncthreads();
-  for (int b = t; b < batch; b += blockDim.x) {
-    int k = sizes[b];
-    if (k < 1 || k > max_n) k = 0;
-    perm[start[k] + atomicAdd(&fill[k], 1)] = b;
+  const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
+  for (int c0 = 0; c0 < batch; c0 += 1024) {
+    const int k = size_of(c0 + t);
+    const int rank = rank_in_wave(k, wcnt[w]);
+    __syncthreads();
+    if (t <= kMaxN) {  // exclusive prefix of the waves' counts, per size
+      int run = 0;
+      for (int v = 0; v < NW; ++v) {
+        const int x = wcnt[v][t];
+        wcnt[v][t] = run;
+        run += x;
+      }
+      ctot[t] = run;
+    }
+    __syncthreads();
+    if (k >= 0) {
+      const int r = coff[k] + wcnt[w][k] + rank;  // rank among all entries of size k
+      const bool odd_last = k > wk && k <= qk && (cnt[k] & 1) && r == cnt[k] - 1;
+      perm[odd_last ? left[k] : start[k] + r] = c0 + t;
+    }
+    __syncthreads();
+    if (t <= kMaxN) coff[t] += ctot[t];
+    for (int e = t; e < NW * (kMaxN + 1); e += 1024) (&wcnt[0][0])[e] = 0;
+    __syncthreads();
   }
 }
 
@@ -648,7 +742,9 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
   const int big_stride = lds_buf(a.max_n, CPLX);
   const int wk = a.wave_max_k > 0 ? a.wave_max_k : 1;
   const int wave_stride = lds_buf(wk, CPLX);
+  const int quad_stride = lds_buf(a.quad_max_k > 0 ? a.quad_max_k : 1, CPLX);
   const int n_items = hdr->n_items, n_large = hdr->n_large, n_small = hdr->n_small;
+  const int n_quad = TOL ? 0 : hdr->n_quad;
   for (;;) {
     if (tid == 0) item_s = atomicAdd(&hdr->counter, 1);
     __syncthreads();
@@ -685,9 +781,30 @@ batched_nn(BatchedArgs a, const int32_t* perm, BatchHdr* hdr) {
           break;
       }
 #undef NN_ONE
+    } else if (!TOL && item < n_large + n_quad / 2) {
+      if constexpr (!TOL) {
+        // a pair of equal-size matrices, four waves each (blocks per wave 1 or 2)
+        const int half = wave / kQuadWaves;
+        const int b =
+            __builtin_amdgcn_readfirstlane(perm[n_large + 2 * (item - n_large) + half]);
+        const Group g{wave % kQuadWaves, kQuadWaves, lane, tid % (kQuadWaves * 64), half, true};
+        const int64_t off = a.offsets[b] * cm, xoff = xoffsets[b] * cm;
+        const int K = __builtin_amdgcn_readfirstlane(a.sizes[b]);
+        const int base = half * lds_nbufs(a.depth) * quad_stride;
+        nn_info_dev* inf = a.info ? a.info + b : nullptr;
+        const int nbw = blocks_per_wave(K, CPLX, kQuadWaves);
+        const bool sh = shared_rows(K, CPLX, nbw);
+#define NN_ONE(NB, SH)                                                                       \
+  invert_one<CPLX, NB, SH, TOL>(A + off, X + xoff, K, a.depth, a.x0, a.iters, a.tol, a.max_iter, \
+                                base, quad_stride, g, inf)
+        if (nbw == 1) NN_ONE(1, true);
+        else if (sh) NN_ONE(2, true);
+        else NN_ONE(2, false);
+#undef NN_ONE
+      }
     } else {
-      const int idx = n_large + kWaves * (item - n_large) + wave;
-      if (idx < n_large + n_small) {
+      const int idx = n_large + n_quad + kWaves * (item - n_large - n_quad / 2) + wave;
+      if (idx < n_large + n_quad + n_small) {
         const int b = __builtin_amdgcn_readfirstlane(perm[idx]);
         const Group g{0, 1, lane, lane, wave, false};
         const int64_t off = a.offsets[b] * cm, xoff = xoffsets[b] * cm;
@@ -729,7 +846,11 @@ size_t lds_bytes(bool cplx, int max_n, int wave_max_k, int depth) {
   const size_t big = nb * (size_t)lds_buf(max_n, cplx);
   const int wk = wave_max_k > 0 ? wave_max_k : 1;
   const size_t small = kWaves * nb * (size_t)lds_buf(wk, cplx);  // one wave matrix per wave
-  return sizeof(float) * (big > small ? big : small);
+  // a pair of fixed-nest matrices (counted whether or not the launch has pairs)
+  const int qk = max_n < kQuadMaxK ? max_n : kQuadMaxK;
+  const size_t quad = qk > wave_max_k ? 2 * nb * (size_t)lds_buf(qk, cplx) : 0;
+  size_t m = big > small ? big : small;
+  return sizeof(float) * (m > quad ? m : quad);
 }
 
 }  // namespace
@@ -742,8 +863,12 @@ hipError_t launch_batched(const BatchedArgs& args, hipStream_t s) {
   int32_t* perm = reinterpret_cast<int32_t*>(static_cast<char*>(a.ws) + 256);
   const bool cplx = a.dt == NN_C64;
   if (a.wave_max_k > a.max_n) a.wave_max_k = a.max_n;
+  // pairs only in the fixed-nest mode: there every matrix meets the same
+  // barriers; in the tolerance mode each stops on its own
+  const int qk = a.max_n < kQuadMaxK ? a.max_n : kQuadMaxK;
+  a.quad_max_k = a.iters > 0 && qk > a.wave_max_k ? qk : a.wave_max_k;
   hipLaunchKernelGGL(batched_plan, dim3(1), dim3(1024), 0, s, a.sizes, a.batch, a.max_n,
-                     a.wave_max_k, hdr, perm, a.info);
+                     a.wave_max_k, a.quad_max_k, hdr, perm, a.info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = lds_bytes(cplx, a.max_n, a.wave_max_k, a.depth);

@@ -207,6 +207,7 @@ struct BatchedArgs {
   double tol = 0.0;
   int max_iter = 0;
   int wave_max_k = 16;
+  int quad_max_k = 0;  // set by launch_batched
   void* ws = nullptr;
   nn_info_dev* info = nullptr;
   int grid = 1;
