@@ -136,6 +136,24 @@ def profile_report(dirs, n=8192):
             print(f"  {int(r['Calls']):7d}  avg {float(r['AverageNs']) / 1e3:11.2f} us  "
                   f"min {float(r['MinNs']) / 1e3:11.2f}  max {float(r['MaxNs']) / 1e3:11.2f}  "
                   f"{float(r['Percentage']):5.1f}%  {r['Name'][:150]}")
+    # the same launches by grid size (one kernel runs at several sizes in a run)
+    by_grid = {}
+    for d in dirs:
+        for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+            for r in _csv_rows(path):
+                g = r.get("Grid_Size") or r.get("Grid_Size_X")
+                w = r.get("Workgroup_Size") or r.get("Workgroup_Size_X")
+                dur = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e6  # ms
+                by_grid.setdefault((r["Kernel_Name"], g, w), []).append(dur)
+    if by_grid:
+        tot = sum(sum(v) for v in by_grid.values())
+        print("launches by grid size (ms): kernel | grid (threads) | workgroup | calls | total | "
+              "avg | min | max")
+        for (k, g, w), v in sorted(by_grid.items(), key=lambda kv: -sum(kv[1]))[:20]:
+            if sum(v) < 0.001 * tot:
+                break
+            print(f"  {k[:110]} | {g} | {w} | {len(v)} | {sum(v):.3f} | {sum(v) / len(v):.4f} | "
+                  f"{min(v):.4f} | {max(v):.4f}")
     for k, cs in counters.items():
         print(f"counters per dispatch: {k[:150]}")
         for c, vals in sorted(cs.items()):
