@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
   constexpr int NW = 1024 / 64;
   __shared__ int cnt[kMaxN + 1], start[kMaxN + 1], left[kMaxN + 1], coff[kMaxN + 1],
       ctot[kMaxN + 1];
-  __shared__ int wcnt[NW][kMaxN + 1];
+  __shared__ int wcnt[NW][kMaxN + 1], wpre[NW][kMaxN + 1];
   __shared__ int bad;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   if (t <= kMaxN) {
@@ -622,9 +622,23 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
     const int k = sizes[b];
     return k < 1 || k > max_n ? 0 : k;
   };
-  // this lane's rank among the lanes of its wave with the same size, and the
-  // wave's count of each size present (written by the first such lane)
-  auto rank_in_wave = [&](int k, int* counts) {
+  // The first kPlanRegs chunks' sizes are loaded once, all at the same time
+  // (each pass over them would otherwise wait for one memory round trip per
+  // chunk); later chunks are read as they come.
+  constexpr int kPlanRegs = 8;
+  int kreg[kPlanRegs];
+#pragma unroll
+  for (int i = 0; i < kPlanRegs; ++i) kreg[i] = size_of(i * 1024 + t);
+  auto size_at = [&](int i) {
+    int k = -1;
+#pragma unroll
+    for (int q = 0; q < kPlanRegs; ++q)
+      if (q == i) k = kreg[q];
+    return i < kPlanRegs ? k : size_of(i * 1024 + t);
+  };
+  // Calls fn(kk, m) once per size kk present in the wave (m: the lanes holding
+  // it) and returns this lane's rank among the lanes with its size.
+  auto per_size = [&](int k, auto fn) {
     int rank = 0;
     uint64_t todo = __ballot(k >= 0);
     while (todo) {
@@ -632,13 +646,14 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
       const int kk = __shfl(k, leader, 64);
       const uint64_t m = __ballot(k == kk);
       if (k == kk) rank = __popcll(m & ((1ull << lane) - 1));
-      if (lane == leader) counts[kk] = __popcll(m);
+      if (lane == leader) fn(kk, m);
       todo &= ~m;
     }
     return rank;
   };
+  // counts (one atomic per wave and size present)
   for (int c0 = 0; c0 < batch; c0 += 1024) {
-    const int k = size_of(c0 + t);
+    const int k = size_at(c0 / 1024);
     if (k == 0) {
       bad = 1;
       if (info) {
@@ -649,18 +664,9 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
         info[c0 + t] = d;
       }
     }
-    (void)rank_in_wave(k, wcnt[w]);
-    __syncthreads();
-    if (t <= kMaxN) {
-      int run = 0;
-      for (int v = 0; v < NW; ++v) {
-        run += wcnt[v][t];
-        wcnt[v][t] = 0;
-      }
-      cnt[t] += run;
-    }
-    __syncthreads();
+    (void)per_size(k, [&](int kk, uint64_t m) { atomicAdd(&cnt[kk], (int)__popcll(m)); });
   }
+  __syncthreads();
   if (t == 0) {
     const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
     int acc = 0;
@@ -692,28 +698,34 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
   __syncthreads();
   const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
   for (int c0 = 0; c0 < batch; c0 += 1024) {
-    const int k = size_of(c0 + t);
-    const int rank = rank_in_wave(k, wcnt[w]);
+    const int k = size_at(c0 / 1024);
+    const int rank = per_size(k, [&](int kk, uint64_t m) { wcnt[w][kk] = (int)__popcll(m); });
     __syncthreads();
-    if (t <= kMaxN) {  // exclusive prefix of the waves' counts, per size
-      int run = 0;
-      for (int v = 0; v < NW; ++v) {
-        const int x = wcnt[v][t];
-        wcnt[v][t] = run;
-        run += x;
+    // exclusive prefix of the waves' counts per size: 16-lane groups, one
+    // size per group, one wave per lane
+    for (int base = 0; base <= kMaxN; base += 1024 / NW) {
+      const int kk = base + (t >> 4), v = t & (NW - 1);
+      const int x = kk <= kMaxN ? wcnt[v][kk] : 0;
+      int incl = x;
+#pragma unroll
+      for (int o = 1; o < NW; o <<= 1) {
+        const int y = __shfl_up(incl, o, NW);
+        if (v >= o) incl += y;
       }
-      ctot[t] = run;
+      if (kk <= kMaxN) {
+        wpre[v][kk] = incl - x;
+        if (v == NW - 1) ctot[kk] = incl;
+      }
     }
     __syncthreads();
+    for (int e = t; e < NW * (kMaxN + 1); e += 1024) (&wcnt[0][0])[e] = 0;
     if (k >= 0) {
-      const int r = coff[k] + wcnt[w][k] + rank;  // rank among all entries of size k
+      const int r = coff[k] + wpre[w][k] + rank;  // rank among all entries of size k
       const bool odd_last = k > wk && k <= qk && (cnt[k] & 1) && r == cnt[k] - 1;
       perm[odd_last ? left[k] : start[k] + r] = c0 + t;
     }
     __syncthreads();
     if (t <= kMaxN) coff[t] += ctot[t];
-    for (int e = t; e < NW * (kMaxN + 1); e += 1024) (&wcnt[0][0])[e] = 0;
-    __syncthreads();
   }
 }
 
