@@ -667,36 +667,46 @@ __global__ void __launch_bounds__(1024) batched_plan(const int32_t* sizes, int b
     (void)per_size(k, [&](int kk, uint64_t m) { atomicAdd(&cnt[kk], (int)__popcll(m)); });
   }
   __syncthreads();
-  if (t == 0) {
-    const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
-    int acc = 0;
-    for (int k = kMaxN; k > qk; --k) {
-      start[k] = acc;
-      acc += cnt[k];
+  const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
+  static_assert(kMaxN == 64, "one lane per size");
+  if (w == 0) {
+    // the region offsets by 64-lane prefix sums, lane l holding size 64 - l
+    // (sizes in descending order along the lanes)
+    const int k = kMaxN - lane, c = cnt[k];
+    auto scan = [&](int x, int* total) {  // exclusive prefix over the lanes
+      int incl = x;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      *total = __shfl(incl, 63, 64);
+      return incl - x;
+    };
+    const bool lg = k > qk, qd = k <= qk && k > wk;
+    int n0, nl, nq, ns;
+    const int a = scan(lg ? c : 0, &n0);                       // large, K descending
+    const int b = scan(qd && (c & 1) ? 1 : 0, &nl);            // one odd one out per pair size
+    const int q = scan(qd ? c & ~1 : 0, &nq);                  // pairs
+    const int sm = scan(!lg && !qd ? c : 0, &ns);              // one wave per matrix
+    const int n_large = n0 + nl;
+    if (lg) start[k] = a;
+    if (qd) {
+      if (c & 1) left[k] = n0 + b;
+      start[k] = n_large + q;
     }
-    for (int k = qk; k > wk; --k)
-      if (cnt[k] & 1) left[k] = acc++;
-    const int n_large = acc;
-    for (int k = qk; k > wk; --k) {
-      start[k] = acc;
-      acc += cnt[k] & ~1;
+    if (!lg && !qd) start[k] = n_large + nq + sm;
+    if (lane == 0) {
+      start[0] = n_large + nq + ns;
+      hdr->counter = 0;
+      hdr->n_large = n_large;
+      hdr->n_quad = nq;
+      hdr->n_small = ns;
+      hdr->n_items = n_large + nq / 2 + (ns + kWaves - 1) / kWaves;
+      hdr->bad = bad;
     }
-    const int n_quad = acc - n_large;
-    for (int k = wk; k >= 1; --k) {
-      start[k] = acc;
-      acc += cnt[k];
-    }
-    const int n_small = acc - n_large - n_quad;
-    start[0] = acc;
-    hdr->counter = 0;
-    hdr->n_large = n_large;
-    hdr->n_quad = n_quad;
-    hdr->n_small = n_small;
-    hdr->n_items = n_large + n_quad / 2 + (n_small + kWaves - 1) / kWaves;
-    hdr->bad = bad;
   }
   __syncthreads();
-  const int wk = wave_max_k, qk = quad_max_k > wave_max_k ? quad_max_k : wave_max_k;
   for (int c0 = 0; c0 < batch; c0 += 1024) {
     const int k = size_at(c0 / 1024);
     const int rank = per_size(k, [&](int kk, uint64_t m) { wcnt[w][kk] = (int)__popcll(m); });
