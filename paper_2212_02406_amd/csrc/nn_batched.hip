@@ -25,9 +25,10 @@
 //    row k of B, row 2k+1 is that row with (re, im) -> (-im, re)).  The whole
 //    product stays in registers until the group barrier, so the output may
 //    overwrite an input buffer (X' = X + X U is written over X).
-//  * results depend only on the matrix and its size class: block-to-wave
-//    assignment and summation orders are fixed, so a matrix gives the same
-//    bits alone or in any batch.
+//  * results depend only on the matrix: every output block is summed over k
+//    in the same order whichever wave holds it, and sums of squares add the
+//    blocks' sums in block order, so a matrix gives the same bits alone or in
+//    any batch, on the whole-group, paired or one-wave path.
 //  * two control modes: a fixed number of nests, or a tolerance mode in which
 //    each matrix applies the stopping rules of the single-matrix path on the
 //    device after every residual (its own tolerance and nest limit), so the
