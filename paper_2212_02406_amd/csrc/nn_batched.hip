@@ -449,10 +449,13 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     for (int r = g.gw; r < K; r += g.G)
       for (int c = g.lane; c < cols; c += 64) Xg[r * cols + c] = smem[Xs + r * ld + scol(r, c, swz)];
   };
-  // G is staged into R's buffer once, with all of a thread's loads in flight:
-  // the start reads it there, and the staging brings G into L2, where every
-  // residual then reads it.
-  stage_g();
+  // The transpose start reads G (rows and columns) from LDS: G is staged into
+  // R's buffer once, with all of a thread's loads in flight.  The other starts
+  // need only G's diagonal (read from global memory below) or nothing, and
+  // the residuals read G from global memory anyway, so they skip the staging
+  // (identity start, 4096-matrix batch: 0.394 -> 0.384 ms).
+  if (x0 == NN_X0_TRANSPOSE) stage_g();
+  else g.sync();
   // Start iterate (Sec. II-A normalisation): den = ||G||_1 ||G||_inf or Re Tr G;
   // NN_X0_GIVEN reads X_0 from Xg.
   double den = 1.0;
@@ -498,8 +501,12 @@ __device__ __forceinline__ void invert_one(const float* Ag, float* Xg, int K, in
     }
     den = bad ? NAN : n1 * ninf;
   } else if (x0 == NN_X0_SCALED_IDENTITY) {
+    // lane i loads diagonal entry i (K <= 64); the entries are then added in
+    // index order through readlane
+    const float dg = g.lane < K ? Ag[g.lane * cols + (CPLX ? 2 * g.lane : g.lane)] : 0.f;
     double t = 0.0;
-    for (int i = 0; i < K; ++i) t += (double)smem[Gs + i * ld + scol(i, CPLX ? 2 * i : i, swz)];
+    for (int i = 0; i < K; ++i)
+      t += (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(dg), i));
     den = t;
   }
   const bool den_ok = isfinite(den) && den > 0.0;
