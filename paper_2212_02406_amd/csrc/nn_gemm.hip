@@ -384,7 +384,12 @@ constexpr int kSmallChunk = 64;
 
 template <typename T, bool CPLX, bool EXACT>
 __global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m, int tiles_n) {
-  if (p.skip && *p.skip) return;
+  // The device-stop flag and (wave 0) the epilogue's E values are loaded
+  // before the operands and tested or used only after the operand loads are
+  // issued, so their latency overlaps instead of adding up (the kernel is
+  // bound by load latency, not arithmetic).  The flag is the same for every
+  // wave: each wave leaves before the workgroup barrier when it is set.
+  const int skipv = p.skip ? *p.skip : 0;
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
   typedef T vec_t __attribute__((ext_vector_type(V)));
@@ -400,6 +405,15 @@ __global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m
   const T* __restrict__ B = static_cast<const T*>(p.B);
   const int64_t arow = m0 + lr, bcol = n0 + lr;
   const bool arow_ok = EXACT || arow < M, bcol_ok = EXACT || bcol < N;
+  const T* __restrict__ E = static_cast<const T*>(p.E);
+  T ev[4] = {T(0), T(0), T(0), T(0)};
+  if (wave == 0 && E) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t r = m0 + Mfma<T>::row(lq, t);
+      if (EXACT || (r < M && bcol < N)) ev[t] = E[r * p.lde + bcol];
+    }
+  }
 
   acc_t acc = acc_t{};
   const int64_t nchunks = (K + kSmallChunk - 1) / kSmallChunk;
@@ -438,9 +452,11 @@ __global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m
         b[j] = (bcol_ok && (EXACT || k < K)) ? B[k * p.ldb + bcol] : T(0);
       }
     }
+    if (skipv) return;
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc = Mfma<T>::run(a[j], b[j], acc);
   }
+  if (skipv) return;  // a wave with no chunk
 
   if (wave > 0) red[wave - 1][lane] = acc;
   __syncthreads();
@@ -449,7 +465,6 @@ __global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m
   for (int w = 0; w < 3; ++w) acc += red[w][lane];
 
   T* __restrict__ C = static_cast<T*>(p.C);
-  const T* __restrict__ E = static_cast<const T*>(p.E);
   const T alpha = (T)p.alpha, diag = (T)p.diag;
   double ss = 0.0;
   const int64_t c = bcol;
@@ -458,7 +473,7 @@ __global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m
     const int64_t r = m0 + Mfma<T>::row(lq, t);
     if (EXACT || (r < M && c < N)) {
       T v = alpha * acc[t];
-      if (E) v += E[r * p.lde + c];
+      if (E) v += ev[t];
       if (CPLX ? (c == 2 * r) : (c == r)) v += diag;
       C[r * p.ldc + c] = v;
       ss += (double)v * (double)v;
