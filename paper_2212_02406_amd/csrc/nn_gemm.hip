@@ -384,11 +384,11 @@ constexpr int kSmallChunk = 64;
 
 template <typename T, bool CPLX, bool EXACT>
 __global__ void __launch_bounds__(256) gemm_small_kernel(GemmArgs p, int tiles_m, int tiles_n) {
-  // The device-stop flag and (wave 0) the epilogue's E values are loaded
-  // before the operands and tested or used only after the operand loads are
-  // issued, so their latency overlaps instead of adding up (the kernel is
-  // bound by load latency, not arithmetic).  The flag is the same for every
-  // wave: each wave leaves before the workgroup barrier when it is set.
+  // Wave 0 loads the epilogue's E values before the operands, so that round
+  // trip overlaps the operand loads instead of following the LDS sum (the
+  // kernel is bound by load latency, not arithmetic).  The device-stop flag
+  // is the same for every wave: each wave leaves before the workgroup barrier
+  // when it is set.
   const int skipv = p.skip ? *p.skip : 0;
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
